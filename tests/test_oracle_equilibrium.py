@@ -1,0 +1,171 @@
+"""Pins for the oracle's equilibria (Sec. V): the exact entropic equilibrium
+E2 and the series equilibrium E1 with its printed error constants."""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _cases(seed=1, n=40):
+    rng = np.random.default_rng(seed)
+    for _ in range(n):
+        rho = rng.uniform(0.5, 2.0)
+        u = rng.uniform(-0.2, 0.2, 3)
+        eta = rng.uniform(-0.1, 0.1)
+        yield rho, u, eta
+
+
+def test_e2_conserves_mass_momentum_energy(orc):
+    """<f_eq, {1, c, c^2}> = {rho, rho u, rho u^2 + 3 rho theta} (Sec. V)."""
+    c, w, t0 = orc.lattice()
+    c2 = (c ** 2).sum(1)
+    for rho, u, eta in _cases():
+        th = t0 * (1 + eta)
+        f, lam, res, it, rc = orc.equilibrium(rho, u, th)
+        assert rc == 0 and it <= 6
+        assert abs(f.sum() / rho - 1) < 1e-14
+        assert np.max(np.abs(f @ c / rho - u)) < 1e-14
+        assert abs((f @ c2) / (rho * (u @ u + 3 * th)) - 1) < 1e-14
+
+
+def test_e2_has_the_exponential_form(orc):
+    """log(f_eq / (rho w)) is exactly affine in (1, c, c^2): the
+    minimiser of H under the five constraints (Sec. V)."""
+    c, w, t0 = orc.lattice()
+    phi = np.column_stack([np.ones(41), c, (c ** 2).sum(1)])
+    for rho, u, eta in _cases(seed=2, n=10):
+        f, lam, *_ = orc.equilibrium(rho, u, t0 * (1 + eta))
+        y = np.log(f / (rho * w))
+        assert np.max(np.abs(y + phi @ lam)) < 1e-13
+
+
+def test_e2_rest_state_at_theta0(orc):
+    """u = 0, theta = theta0 has all multipliers zero, so f_eq = rho w
+    (Sec. V, the reference state)."""
+    _, w, t0 = orc.lattice()
+    f, lam, res, it, rc = orc.equilibrium(1.3, (0.0, 0.0, 0.0), t0)
+    assert np.max(np.abs(lam)) < 1e-15
+    assert np.max(np.abs(f - 1.3 * w)) < 1e-15
+
+
+def test_e2_minimises_H(orc):
+    """H(f_eq) < H(f_eq + d) for every d that keeps the five moments
+    (Sec. V, the H-function and its constrained minimiser)."""
+    c, w, t0 = orc.lattice()
+    phi = np.column_stack([np.ones(41), c, (c ** 2).sum(1)])
+    q, _ = np.linalg.qr(phi, mode="complete")
+    null = q[:, 5:]
+    rng = np.random.default_rng(3)
+    for rho, u, eta in _cases(seed=4, n=8):
+        f, *_ = orc.equilibrium(rho, u, t0 * (1 + eta))
+        h0 = orc.entropy(f)
+        for _ in range(20):
+            d = null @ rng.normal(size=36)
+            d *= 1e-3 * f.min() / np.max(np.abs(d))
+            assert np.max(np.abs(phi.T @ d)) < 1e-15
+            assert orc.entropy(f + d) > h0
+
+
+def test_e2_cubic_equivariance(orc):
+    c, w, t0 = orc.lattice()
+    key = {tuple(v): i for i, v in enumerate(c.tolist())}
+    u = np.array([0.11, -0.05, 0.03])
+    th = t0 * 1.04
+    f0, *_ = orc.equilibrium(1.0, u, th)
+    for perm in itertools.permutations(range(3)):
+        for sg in itertools.product((-1.0, 1.0), repeat=3):
+            sg = np.array(sg)
+            img = (c[:, perm] * sg).tolist()
+            idx = [key[tuple(v)] for v in img]  # velocity i maps to idx[i]
+            u2 = np.zeros(3)
+            u2[:] = (u[list(perm)] * sg)
+            f2, *_ = orc.equilibrium(1.0, u2, th)
+            assert np.max(np.abs(f2[idx] - f0)) < 1e-15
+
+
+def test_e2_pressure_tensor_is_euler_to_fourth_order(orc):
+    """P = rho theta delta + rho u u up to O(u^4) on this lattice."""
+    c, w, t0 = orc.lattice()
+    errs = []
+    for s in (0.025, 0.05, 0.1):
+        u = np.array([1.0, 0.0, 0.0]) * s
+        f, *_ = orc.equilibrium(1.0, u, t0)
+        P = np.einsum("q,qa,qb->ab", f, c, c)
+        # the E2 temperature is the kinetic one, so trace matches exactly
+        ref = t0 * np.eye(3) + np.outer(u, u)
+        errs.append(np.max(np.abs(P - ref)))
+    assert errs[2] < 2e-5
+    assert 12 < errs[1] / errs[0] < 20 and 12 < errs[2] / errs[1] < 20
+
+
+def test_e2_matches_series_to_fourth_order(orc):
+    """E2 - E1 = O(u^4) at theta0 and O(eta^4) at rest."""
+    _, _, t0 = orc.lattice()
+    d = []
+    for s in (1e-3, 2e-3, 4e-3):
+        u = np.array([1.0, 0.5, -0.3]) * s
+        d.append(np.max(np.abs(orc.equilibrium(1.0, u, t0)[0] - orc.equilibrium_series(1.0, u, t0))))
+    assert d[0] < 1e-12
+    assert 14 < d[1] / d[0] < 18 and 14 < d[2] / d[1] < 18
+    d = []
+    for eta in (2e-3, 4e-3, 8e-3):
+        d.append(np.max(np.abs(orc.equilibrium(1.0, (0, 0, 0), t0 * (1 + eta))[0] - orc.series_rest(1.0, eta))))
+    assert 14 < d[1] / d[0] < 18 and 14 < d[2] / d[1] < 18
+
+
+def _printed_constants():
+    out = {}
+    with open(os.path.join(GOLDEN, "series_error_constants.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            p = line.split()
+            out[p[0]] = (int(p[1]), float(p[2]), float(p[3]), float(p[4]), float(p[5]))
+    return out
+
+
+@pytest.mark.parametrize("eta", [-0.08, -0.03, 0.02, 0.05, 0.1])
+def test_series_error_terms_match_printed_constants(orc, eta):
+    """M2, M2', M3, M3' from the lattice sums reproduce the coefficients the
+    paper prints (Sec. V) to their printed precision."""
+    pr = _printed_constants()
+    m = orc.series_errors(eta)
+    for name, val in zip(("M2", "M2p", "M3", "M3p"), m):
+        power, pre, c1, c2, c3 = pr[name]
+        printed = pre * (c1 * eta + c2 * eta ** 2 + c3 * eta ** 3) / (1 + eta) ** power
+        # six printed significant digits
+        assert abs(val - printed) <= 2e-6 * (abs(pre) * (abs(c1 * eta) + abs(c2) * eta ** 2 + abs(c3 * eta ** 3))) + 1e-16, (name, val, printed)
+
+
+def test_series_rest_conserves_mass_and_energy(orc):
+    """<f~, 1> = rho and <f~, c^2> = 3 rho theta for any eta (Sec. V)."""
+    c, w, t0 = orc.lattice()
+    c2 = (c ** 2).sum(1)
+    for eta in (-0.2, -0.05, 0.03, 0.1, 0.3):
+        f = orc.series_rest(1.7, eta)
+        assert abs(f.sum() / 1.7 - 1) < 1e-15
+        assert abs((f @ c2) / (3 * 1.7 * t0 * (1 + eta)) - 1) < 2e-15
+
+
+def test_series_equilibrium_conserves_mass_and_energy(orc):
+    """The series equilibrium E1 keeps mass and energy exactly (A1 is the
+    value that makes the energy exact)."""
+    c, w, t0 = orc.lattice()
+    c2 = (c ** 2).sum(1)
+    for rho, u, eta in _cases(seed=5, n=20):
+        th = t0 * (1 + eta)
+        f = orc.equilibrium_series(rho, u, th)
+        assert abs(f.sum() / rho - 1) < 1e-14
+        assert abs((f @ c2) / (rho * (u @ u + 3 * th)) - 1) < 1e-14
+
+
+def test_series_equilibrium_momentum_error_is_anisotropic_cubic(orc):
+    """E1's momentum differs from rho u only at O(u^3 eta^k): at theta0 it
+    is exact up to the fourth-order remainder."""
+    c, w, t0 = orc.lattice()
+    u = np.array([0.01, -0.02, 0.005])
+    f = orc.equilibrium_series(1.0, u, t0)
+    assert np.max(np.abs(f @ c - u)) < 1e-12

@@ -1,0 +1,102 @@
+"""Physics pins for the oracle: the isentropic sound speed sqrt(gamma theta0)
+(Sec. I and Sec. VI) and acoustic/thermal decay against the linearised
+Navier-Stokes-Fourier equations (Sec. I), plus pins of the analysis
+helpers themselves against textbook limits."""
+import numpy as np
+import pytest
+
+from oracle import analysis as an
+from paper_1909_08406_amd import workloads as wl
+
+
+def test_nsf_small_k_limits():
+    """Textbook long-wave limits: acoustic speed sqrt(gamma theta0),
+    attenuation (1/2)[(4/3) nu + (gamma - 1) chi] k^2, entropy mode chi k^2."""
+    th0, nu, chi = 0.29, 0.03, 0.05
+    for k in (1e-3, 3e-3):
+        ac, ent = an.nsf_modes(k, nu, chi, th0)
+        assert abs(ac.imag / k / np.sqrt(an.GAMMA * th0) - 1) < 1e-5
+        att = 0.5 * ((4 / 3) * nu + (an.GAMMA - 1) * chi) * k * k
+        assert abs(-ac.real / att - 1) < 1e-4
+        assert abs(-ent / (chi * k * k) - 1) < 1e-4
+    # inviscid: purely oscillating acoustic pair and a neutral entropy mode
+    ac, ent = an.nsf_modes(0.2, 0.0, 0.0, th0)
+    assert abs(ac.real) < 1e-14 and abs(ent) < 1e-14
+    assert abs(ac.imag - 0.2 * np.sqrt(an.GAMMA * th0)) < 1e-14
+
+
+def test_pulse_closed_form_matches_integral():
+    """The d'Alembert form of the 3D pulse equals the wavenumber integral and
+    starts as eps exp(-ln2 r^2/b^2)."""
+    r = np.array([0.0, 1.0, 4.0, 8.0, 15.0, 30.0])
+    for t in (0.0, 5.0, 20.0):
+        a = an.pulse_3d(r, t, 1e-3, 8.0, 0.7)
+        b = an.pulse_3d_integral(r, t, 1e-3, 8.0, 0.7)
+        assert np.max(np.abs(a - b)) < 1e-12
+    assert np.allclose(an.pulse_3d(r, 0.0, 1e-3, 8.0, 0.7), 1e-3 * np.exp(-np.log(2) * r * r / 64), rtol=0, atol=1e-16)
+
+
+def test_fourier_projection_of_a_sine():
+    nx, ny, nz = 16, 2, 2
+    F = wl.standing_wave(nx, ny, nz, amp=2e-3, k=3, axis=0)
+    a = an.fourier_mode(F.rho - 1.0, nx, ny, nz, (2 * np.pi * 3 / nx, 0, 0))
+    assert abs(-2 * a.imag - 2e-3) < 1e-15 and abs(a.real) < 1e-16
+
+
+def _run_modes(orc, nx, ny, nz, tau, steps, fields, kvec, which):
+    _, _, th0 = orc.lattice()
+    f = orc.init(nx, ny, nz, *fields.absolute(th0))
+    amps = []
+    tot0 = orc.totals(f)
+    for s in range(steps + 1):
+        if s:
+            f = orc.run(nx, ny, nz, 1.0 / tau, f, 1)
+        m = orc.moment_fields(f)
+        fld = m[0] - 1.0 if which == "rho" else an.temperature(*m) - th0
+        amps.append(an.fourier_mode(fld, nx, ny, nz, kvec))
+    return np.array(amps), tot0, orc.totals(f), th0
+
+
+@pytest.mark.slow
+def test_standing_acoustic_wave_32x16x16(orc):
+    """Plain method, FP64, 32x16x16 box, rho = 1 + 1e-3 sin(2 pi x/32),
+    tau_lb = 0.6, 200 steps: sound speed within 0.1% of sqrt(gamma theta0),
+    acoustic and entropy decay within 1% of linearised NSF, 3/5 of the
+    amplitude acoustic and 2/5 entropic (constant-temperature start), and
+    global mass and energy conserved."""
+    nx, ny, nz, tau = 32, 16, 16, 0.6
+    k = 2 * np.pi / nx
+    F = wl.standing_wave(nx, ny, nz, 1e-3, 1, 0)
+    a, tot0, tot, th0 = _run_modes(orc, nx, ny, nz, tau, 200, F, (k, 0, 0), "rho")
+    sig = -2 * a.imag
+    nu = an.viscosity(th0, tau)
+    ac, ent = an.nsf_modes(k, nu, nu, th0)
+    fit = an.fit_acoustic_entropy(np.arange(201)[10:], sig[10:], ac.imag, -ac.real)
+    cs = np.sqrt(an.GAMMA * th0)
+    assert abs(fit["w"] / k / cs - 1) < 1e-3
+    assert abs(fit["G"] / -ac.real - 1) < 1e-2
+    assert abs(fit["Ge"] / -ent - 1) < 1e-2
+    assert abs(fit["A"] / 1e-3 - 0.6) < 2e-3 and abs(fit["B"] / 1e-3 - 0.4) < 2e-3
+    assert abs(tot[0] / tot0[0] - 1) < 1e-13
+    assert abs(tot[4] / tot0[4] - 1) < 1e-13
+    assert np.max(np.abs(tot[1:4])) < 1e-13 * tot0[0]
+
+
+@pytest.mark.slow
+def test_thermal_mode_decay(orc):
+    """Temperature mode theta = theta0 (1 + 1e-3 cos(2 pi z/32)) decays at
+    the NSF entropy-mode rate (Fourier heat conduction at Prandtl 1)."""
+    nx, ny, nz, tau = 4, 4, 32, 0.55
+    k = 2 * np.pi / nz
+    x, y, z = wl.positions(nx, ny, nz)
+    F = wl.standing_wave(nx, ny, nz, 0.0)
+    F.theta_rel = 1.0 + 1e-3 * np.cos(k * z)
+    a, *_ , th0 = _run_modes(orc, nx, ny, nz, tau, 300, F, (0, 0, k), "theta")
+    sig = 2 * a.real
+    nu = an.viscosity(th0, tau)
+    ac, ent = an.nsf_modes(k, nu, nu, th0)
+    fit = an.fit_acoustic_entropy(np.arange(301)[10:], sig[10:], ac.imag, -ac.real)
+    assert abs(fit["Ge"] / -ent - 1) < 1e-2
+    assert abs(fit["w"] / k / np.sqrt(an.GAMMA * th0) - 1) < 1e-3
+    # entropy part carries 1/gamma of the initial temperature jump
+    assert abs(fit["B"] / (1e-3 * th0) - 0.6) < 5e-3
