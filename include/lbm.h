@@ -1,0 +1,212 @@
+/*
+ * liblbm: fused collide-and-stream update of the RD3Q41 energy-conserving
+ * lattice Boltzmann method on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: P. K. Kolluru, M. Atif, M. Namburi, S. Ansumali, "Lattice Boltzmann
+ * model for weakly compressible flows" (arXiv:1909.08406).
+ *   - State: 41 populations f_i per node (Sec. II), on the RD3Q41 velocity
+ *     set of Table I (Sec. IV): rest, sc-1, sc-2, fcc-1, bcc-1, bcc-1/2.
+ *   - Grid: a body-centred cubic lattice, i.e. two simple-cubic sublattices
+ *     offset by half a spacing (Sec. IV). A box of nx*ny*nz cells has
+ *     N = 2*nx*ny*nz nodes; node (s, x, y, z) sits at (x, y, z) + s/2*(1,1,1).
+ *     Node id n = ((s*nz + z)*ny + y)*nx + x. All boxes are fully periodic.
+ *   - Update: discrete BGK, f_i(x + c_i, t + 1) = f_i + omega (f_i^eq - f_i)
+ *     (Sec. II; omega is the paper's 2*beta), with f^eq the exact entropic
+ *     equilibrium w_i rho exp(-alpha - beta.c_i - gamma c_i^2) whose
+ *     multipliers reproduce rho, rho u and rho u^2 + 3 rho theta (Sec. V).
+ *     Mass, momentum and energy are conserved by every collision.
+ *   - Observables: rho = <f,1>, j = <f,c>, E = <f,c^2/2> (Sec. II).
+ *
+ * Velocity order (shared by every array indexed by q): q = 0 rest, then the
+ * shells in the order of Table I, each sorted in descending lexicographic
+ * order of (cx, cy, cz). lbm_lattice() returns the table.
+ *
+ * Streaming is "pull": the populations held after a step are the
+ * post-collision values at their node of origin, g = C[f]. Because the
+ * collision conserves rho, j and E, the moments of g equal those of the
+ * pre-collision state f of a collide-then-push description.
+ *
+ * Conventions for every entry point:
+ *   - Host arrays are FP64, box after box; inside a box node fields are
+ *     [s][z][y][x] (x fastest) and populations are [q][node].
+ *   - The caller owns every host pointer and keeps it; the library copies
+ *     what it needs before returning. Device memory is owned by the context
+ *     (allocated by the library, or a caller-supplied workspace that must
+ *     outlive the context).
+ *   - Calls are asynchronous on the context stream unless stated otherwise.
+ *   - Return value: LBM_OK (0) or a negative lbm_error. Nothing throws
+ *     across this interface. lbm_strerror() is thread-safe. A context is
+ *     not thread-safe: calls on one context must not overlap.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_Q 41
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_E_ARG = -1,         /* invalid argument (NULL pointer, bad size, tau <= 1/2, ...) */
+    LBM_E_NOMEM = -2,       /* device or host allocation failed, or workspace too small */
+    LBM_E_DOMAIN = -3,      /* unrealisable input: rho <= 0, theta <= 0 or non-finite field */
+    LBM_E_NONFINITE = -4,   /* a step produced rho <= 0, theta <= 0 or a non-finite moment */
+    LBM_E_HIP = -5,         /* a HIP runtime call failed */
+    LBM_E_UNSUPPORTED = -6  /* valid request this build or device cannot serve */
+} lbm_error;
+
+/* How populations are held in device memory (arithmetic type in brackets). */
+typedef enum {
+    LBM_F64 = 0,        /* f in FP64                          [FP64] */
+    LBM_F32 = 1,        /* f in FP32                          [FP32] */
+    LBM_F16_SHIFT = 2,  /* FP16 of (f - w_q rho0) * 2^k_q     [FP32] */
+    LBM_BF16_SHIFT = 3  /* BF16 of (f - w_q rho0) * 2^k_q     [FP32] */
+} lbm_storage;
+
+/* Meaning of lbm_box.tau. */
+typedef enum {
+    LBM_TAU_LB = 0,     /* lattice relaxation time: omega = 1/tau, tau > 1/2           */
+    LBM_TAU_PAPER = 1   /* the paper's mean free time (Sec. II): omega = 2/(2 tau + 1) */
+} lbm_tau_conv;
+
+/* One periodic box of nx*ny*nz cells (2 nodes per cell). */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t reserved;   /* must be 0 */
+    double tau;         /* relaxation time, read per lbm_opts.tau_conv */
+} lbm_box;
+
+#define LBM_SHIFT_AUTO (-1000)
+
+typedef struct {
+    int32_t storage;      /* lbm_storage */
+    int32_t tau_conv;     /* lbm_tau_conv */
+    double rho0;          /* reference density of the shifted storage (0 means 1.0) */
+    int32_t newton_iters; /* Newton steps of the equilibrium solve; 0 = default
+                             (1 with FP32 arithmetic, 3 with FP64) */
+    int32_t shift_exp;    /* k_amp of the shifted storage, k_q = k_shell(q) + k_amp;
+                             LBM_SHIFT_AUTO picks it from the initial state */
+    uint32_t flags;       /* 0; reserved */
+    int32_t reserved;     /* must be 0 */
+} lbm_opts;
+
+/* Read-only facts about a context. */
+typedef struct {
+    int32_t storage;
+    int32_t newton_iters;
+    int32_t shift_exp;          /* k_amp in use (shifted storage), else 0 */
+    int32_t nboxes;
+    int64_t nodes;              /* total nodes over all boxes */
+    int64_t bytes_per_step;     /* algorithmic HBM bytes of one step: 82 * nodes * sizeof(storage) */
+    int32_t block_threads;      /* launch configuration of the step kernel */
+    int32_t variant;            /* step-kernel variant id */
+    uint64_t device_bytes;      /* device memory held by the context */
+} lbm_info;
+
+typedef struct lbm_ctx lbm_ctx; /* opaque, owned by the library */
+
+/*
+ * Lattice constants of Table I (Sec. IV): velocities c[41][3], weights w[41]
+ * (the rest weight is 1 - sum of the printed ones) and the reference
+ * temperature theta0 = sum_i w_i c_ix^2 (Sec. III). Any pointer may be NULL.
+ * No device needed.
+ */
+int lbm_lattice(double *c, double *w, double *theta0);
+
+/*
+ * Device bytes a context with these boxes and options needs (two population
+ * buffers plus staging). No device needed. Errors: LBM_E_ARG.
+ */
+int lbm_workspace_size(const lbm_box *boxes, int32_t nboxes, const lbm_opts *opts, uint64_t *bytes);
+
+/*
+ * Create a context and set every node to the equilibrium of the given
+ * fields, f = f^eq(rho, u, theta) (the fields are nodal FP64 arrays of the
+ * total node count; theta in lattice units, e.g. theta0 for the rest
+ * state). stream: a hipStream_t, or NULL for a stream the library creates.
+ * workspace/workspace_bytes: device memory of at least lbm_workspace_size()
+ * bytes for the context to use, or NULL/0 to let the library allocate it.
+ * Synchronises the stream before returning.
+ * Errors: LBM_E_ARG (NULL pointer, nboxes < 1, dimension < 1, tau out of
+ * range, unknown storage, a q-block over 4 GiB), LBM_E_DOMAIN (rho <= 0,
+ * theta <= 0 or non-finite), LBM_E_NOMEM, LBM_E_HIP.
+ */
+int lbm_init(lbm_ctx **out, const lbm_box *boxes, int32_t nboxes, const lbm_opts *opts,
+             const double *rho, const double *ux, const double *uy, const double *uz,
+             const double *theta, void *stream, void *workspace, uint64_t workspace_bytes);
+
+/* n >= 0 fused collide-and-stream steps of every box (Sec. II), async. */
+int lbm_step(lbm_ctx *ctx, int32_t n);
+
+/* Wait for all work queued on the context stream. */
+int lbm_synchronize(lbm_ctx *ctx);
+
+/*
+ * Per-node FP64 moments rho, jx, jy, jz, E (arrays of the total node count;
+ * any may be NULL). Synchronous. Errors: LBM_E_ARG, LBM_E_HIP.
+ */
+int lbm_moments(lbm_ctx *ctx, double *rho, double *jx, double *jy, double *jz, double *energy);
+
+/*
+ * Global conservation totals per box, summed in FP64 on the device:
+ * out[5*b + k] = (mass, Jx, Jy, Jz, E)[k] of box b. Synchronous.
+ * Returns LBM_E_NONFINITE if any step since init flagged a node with
+ * rho <= 0, theta <= 0 or a non-finite moment (out is still written).
+ */
+int lbm_totals(lbm_ctx *ctx, double *out);
+
+/* LBM_OK, or LBM_E_NONFINITE once a step has flagged a node. Synchronous. */
+int lbm_status(lbm_ctx *ctx);
+
+/*
+ * Copy the held populations to the host as FP64, f[box][q][node] (shifted
+ * storage decoded as w_q rho0 + h 2^-k_q, exactly). Synchronous.
+ */
+int lbm_get_populations(lbm_ctx *ctx, double *f);
+
+/* Overwrite the held populations from FP64 host values (rounded to the
+ * storage type, round-to-nearest-even). Synchronous. */
+int lbm_set_populations(lbm_ctx *ctx, const double *f);
+
+/*
+ * Held populations at selected entries of one box: out[i] = f[q][node] for
+ * idx[i] = q*N_box + node, decoded to FP64. Synchronous.
+ * Errors: LBM_E_ARG for an index outside [0, 41*N_box).
+ */
+int lbm_gather(lbm_ctx *ctx, int32_t box, const int64_t *idx, int64_t count, double *out);
+
+/*
+ * Streaming map of one box as the step kernel computes it: src[q*N + n] is
+ * the node whose population q the step pulls into node n. Synchronous.
+ */
+int lbm_debug_pull_map(lbm_ctx *ctx, int32_t box, int64_t *src);
+
+/* Facts about the context (see lbm_info). */
+int lbm_get_info(lbm_ctx *ctx, lbm_info *info);
+
+/* The hipStream_t the context queues its work on. */
+void *lbm_stream(lbm_ctx *ctx);
+
+/* Release device memory the library allocated and the context itself. */
+void lbm_free(lbm_ctx *ctx);
+
+/* Static description of an error code. */
+const char *lbm_strerror(int code);
+
+/*
+ * Host-only self test of the library's integer helpers (division by
+ * invariant integers used for node decoding). Returns LBM_OK or LBM_E_ARG.
+ * No device needed.
+ */
+int lbm_selftest(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -58,6 +58,7 @@ def _load():
         "orc_collide_node": (i, [_dp, d, _dp]),
         "orc_pull_map": (None, [i, i, i, _lp]),
         "orc_push_map": (None, [i, i, i, _lp]),
+        "orc_pull_src_nodes": (None, [i, i, i, _lp, l, _lp]),
         "orc_init": (i, [i, i, i, _dp, _dp, _dp, _dp, _dp, _dp]),
         "orc_collide_field": (i, [i, i, i, d, _dp, _dp]),
         "orc_run": (i, [i, i, i, d, _dp, _dp, i]),
@@ -155,6 +156,14 @@ def pull_map(nx, ny, nz):
     out = np.zeros(NQ * n, dtype=np.int64)
     _load().orc_pull_map(nx, ny, nz, out.ctypes.data_as(_lp))
     return out.reshape(NQ, n)
+
+
+def pull_sources(nx, ny, nz, nodes):
+    """[len(nodes), 41] source node of each population arriving at each node."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64).reshape(-1)
+    out = np.zeros(nodes.size * NQ, dtype=np.int64)
+    _load().orc_pull_src_nodes(nx, ny, nz, nodes.ctypes.data_as(_lp), nodes.size, out.ctypes.data_as(_lp))
+    return out.reshape(nodes.size, NQ)
 
 
 def push_map(nx, ny, nz):

@@ -449,6 +449,18 @@ void orc_pull_map(int nx, int ny, int nz, int64_t *src)
         }
 }
 
+/* Sources of population q = 0..40 for a list of destination nodes:
+ * src[i*41 + q] (sampled checks on grids too large for a full map). */
+void orc_pull_src_nodes(int nx, int ny, int nz, const int64_t *nodes, int64_t count, int64_t *src)
+{
+    lattice_build();
+    for (int64_t i = 0; i < count; ++i) {
+        int64_t n = nodes[i];
+        int64_t x = n % nx, y = (n / nx) % ny, z = (n / ((int64_t)nx * ny)) % nz, s = n / ((int64_t)nx * ny * nz);
+        for (int q = 0; q < NQ; ++q) src[i * NQ + q] = pull_src(q, s, x, y, z, nx, ny, nz);
+    }
+}
+
 /* dst[q*N + n] = node that population q leaving node n reaches in one step. */
 void orc_push_map(int nx, int ny, int nz, int64_t *dst)
 {

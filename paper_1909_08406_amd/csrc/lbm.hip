@@ -1,0 +1,612 @@
+// Host side of liblbm: the C-ABI declared in include/lbm.h.
+//
+// Device layout of a context (one allocation, or a caller workspace):
+//   buffer A | buffer B | flag | partial sums | staging
+// Each population buffer holds every box in turn, each box as 41 q-blocks
+// of N_box values ([q][s][z][y][x], x fastest). A step reads the current
+// buffer and writes the other (ping-pong), so streaming never races.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "kernels.hpp"
+
+using namespace lbm;
+
+namespace {
+
+constexpr uint64_t STAGING_MAX = 256ull << 20;  // bytes of the host<->device staging area
+constexpr uint64_t ALIGN = 256;
+
+uint64_t align_up(uint64_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+int elem_bytes(int storage)
+{
+    switch (storage) {
+        case LBM_F64: return 8;
+        case LBM_F32: return 4;
+        case LBM_F16_SHIFT:
+        case LBM_BF16_SHIFT: return 2;
+        default: return 0;
+    }
+}
+
+struct BoxDev {
+    Geom g;
+    double omega;
+    uint64_t offset;  // element offset of this box in a population buffer
+    uint64_t nodes;
+};
+
+struct Layout {
+    uint64_t elems = 0;      // elements per population buffer
+    uint64_t buf_bytes = 0;  // bytes per population buffer (aligned)
+    uint64_t flag_off = 0, partial_off = 0, staging_off = 0, staging_bytes = 0, total = 0;
+    uint64_t max_nodes = 0;
+};
+
+int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
+{
+    if (!boxes || !opts || nboxes < 1) return LBM_E_ARG;
+    const int eb = elem_bytes(opts->storage);
+    if (eb == 0) return LBM_E_ARG;
+    if (opts->tau_conv != LBM_TAU_LB && opts->tau_conv != LBM_TAU_PAPER) return LBM_E_ARG;
+    if (opts->newton_iters < 0 || opts->newton_iters > 4) return LBM_E_ARG;
+    if (opts->reserved != 0 || opts->flags != 0) return LBM_E_ARG;
+    if (!(opts->rho0 >= 0.0) || !std::isfinite(opts->rho0)) return LBM_E_ARG;
+    if (opts->shift_exp != LBM_SHIFT_AUTO && (opts->shift_exp < -60 || opts->shift_exp > 60)) return LBM_E_ARG;
+    for (int b = 0; b < nboxes; ++b) {
+        const lbm_box& x = boxes[b];
+        if (x.nx < 1 || x.ny < 1 || x.nz < 1 || x.reserved != 0) return LBM_E_ARG;
+        const uint64_t nodes = 2ull * uint64_t(x.nx) * uint64_t(x.ny) * uint64_t(x.nz);
+        // node ids and in-q-block byte offsets are 32-bit
+        if (nodes >= (1ull << 32) || nodes * uint64_t(eb) > 0xffffffffull) return LBM_E_ARG;
+        if (!std::isfinite(x.tau)) return LBM_E_ARG;
+        if (opts->tau_conv == LBM_TAU_LB && !(x.tau > 0.5)) return LBM_E_ARG;
+        if (opts->tau_conv == LBM_TAU_PAPER && !(x.tau > 0.0)) return LBM_E_ARG;
+    }
+    return LBM_OK;
+}
+
+Layout plan(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
+{
+    Layout L;
+    const int eb = elem_bytes(opts->storage);
+    for (int b = 0; b < nboxes; ++b) {
+        const uint64_t nodes = 2ull * uint64_t(boxes[b].nx) * boxes[b].ny * boxes[b].nz;
+        L.elems += uint64_t(Q) * nodes;
+        L.max_nodes = std::max(L.max_nodes, nodes);
+    }
+    L.buf_bytes = align_up(L.elems * eb);
+    L.flag_off = 2 * L.buf_bytes;
+    L.partial_off = L.flag_off + ALIGN;
+    L.staging_off = L.partial_off + align_up(uint64_t(TOTAL_BLOCKS) * 5 * sizeof(double) + 5 * sizeof(double));
+    // staging holds chunks of FP64 node fields (5 per node) or populations
+    const uint64_t want = std::max<uint64_t>(L.max_nodes * 8 * uint64_t(Q), 4096);
+    L.staging_bytes = align_up(std::min(want, STAGING_MAX));
+    L.total = L.staging_off + L.staging_bytes;
+    return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    std::vector<BoxDev> boxes;
+    int storage = 0;
+    int newton = 1;
+    int kamp = 0;
+    double rho0 = 1.0;
+    Layout L;
+    char* mem = nullptr;
+    bool own_mem = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int cur = 0;  // population buffer holding the current state
+    StepParams base{};  // per-context part of the kernel parameters
+    uint32_t* flag = nullptr;
+    double* partials = nullptr;
+    char* staging = nullptr;
+    int block_threads = BLOCK;
+    int variant = 0;
+
+    char* buf(int i) const { return mem + uint64_t(i) * L.buf_bytes; }
+    StepParams params(const BoxDev& b) const
+    {
+        StepParams p = base;
+        p.g = b.g;
+        p.omega = b.omega;
+        p.omega_f = float(b.omega);
+        return p;
+    }
+};
+
+#define HIPCHK(expr)                                  \
+    do {                                              \
+        if ((expr) != hipSuccess) return LBM_E_HIP;   \
+    } while (0)
+
+namespace {
+
+template <class F>
+int dispatch_storage(int storage, F&& f)
+{
+    switch (storage) {
+        case LBM_F64: return f(StoreF64{});
+        case LBM_F32: return f(StoreF32{});
+        case LBM_F16_SHIFT: return f(StoreF16S{});
+        case LBM_BF16_SHIFT: return f(StoreBF16S{});
+        default: return LBM_E_ARG;
+    }
+}
+
+uint32_t nblocks(uint64_t n) { return uint32_t((n + BLOCK - 1) / BLOCK); }
+
+template <class ST>
+int launch_step_typed(lbm_ctx* ctx, const BoxDev& b, const typename ST::T* in, typename ST::T* out)
+{
+    const StepParams p = ctx->params(b);
+    const dim3 grid(nblocks(b.nodes)), block(BLOCK);
+    switch (ctx->newton) {
+        case 1: hipLaunchKernelGGL((k_step<ST, 1>), grid, block, 0, ctx->stream, in, out, p); break;
+        case 2: hipLaunchKernelGGL((k_step<ST, 2>), grid, block, 0, ctx->stream, in, out, p); break;
+        case 3: hipLaunchKernelGGL((k_step<ST, 3>), grid, block, 0, ctx->stream, in, out, p); break;
+        case 4: hipLaunchKernelGGL((k_step<ST, 4>), grid, block, 0, ctx->stream, in, out, p); break;
+        default: return LBM_E_ARG;
+    }
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+}
+
+int launch_step(lbm_ctx* ctx, const BoxDev& b)
+{
+    return dispatch_storage(ctx->storage, [&](auto st) {
+        using ST = decltype(st);
+        using T = typename ST::T;
+        const T* in = reinterpret_cast<const T*>(ctx->buf(ctx->cur)) + b.offset;
+        T* out = reinterpret_cast<T*>(ctx->buf(1 - ctx->cur)) + b.offset;
+        return launch_step_typed<ST>(ctx, b, in, out);
+    });
+}
+
+// Copy nodal FP64 fields of box b chunk by chunk and run the init kernel.
+int run_init(lbm_ctx* ctx, const BoxDev& b, uint64_t node_base, const double* const fields[5], int mode,
+             float* maxdev)
+{
+    const uint64_t chunk = ctx->L.staging_bytes / (5 * sizeof(double));
+    double* stage = reinterpret_cast<double*>(ctx->staging);
+    for (uint64_t n0 = 0; n0 < b.nodes; n0 += chunk) {
+        const uint64_t cnt = std::min(chunk, b.nodes - n0);
+        for (int k = 0; k < 5; ++k)
+            HIPCHK(hipMemcpyAsync(stage + k * cnt, fields[k] + node_base + n0, cnt * sizeof(double),
+                                  hipMemcpyHostToDevice, ctx->stream));
+        const StepParams p = ctx->params(b);
+        int rc = dispatch_storage(ctx->storage, [&](auto st) {
+            using ST = decltype(st);
+            using T = typename ST::T;
+            T* f = reinterpret_cast<T*>(ctx->buf(ctx->cur)) + b.offset;
+            hipLaunchKernelGGL((k_init<ST>), dim3(nblocks(cnt)), dim3(BLOCK), 0, ctx->stream, f, uint32_t(b.nodes),
+                               uint32_t(n0), uint32_t(cnt), stage, p, mode, maxdev);
+            return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+        });
+        if (rc) return rc;
+        // the staging area is reused by the next chunk
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return LBM_OK;
+}
+
+void set_shift(lbm_ctx* ctx)
+{
+    for (int s = 0; s < 6; ++s) {
+        const int k = ctx->kamp + SHELL_K[s];
+        ctx->base.scale[s] = std::ldexp(1.0f, k);
+        ctx->base.inv_scale[s] = std::ldexp(1.0f, -k);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_lattice(double* c, double* w, double* theta0)
+{
+    for (int q = 0; q < Q; ++q) {
+        if (c) {
+            c[3 * q + 0] = 0.5 * VEL[q].x;
+            c[3 * q + 1] = 0.5 * VEL[q].y;
+            c[3 * q + 2] = 0.5 * VEL[q].z;
+        }
+        if (w) w[q] = SHELL_W[VEL[q].shell];
+    }
+    if (theta0) *theta0 = THETA0;
+    return LBM_OK;
+}
+
+int lbm_workspace_size(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts, uint64_t* bytes)
+{
+    if (!bytes) return LBM_E_ARG;
+    int rc = check_boxes(boxes, nboxes, opts);
+    if (rc) return rc;
+    *bytes = plan(boxes, nboxes, opts).total;
+    return LBM_OK;
+}
+
+int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts, const double* rho,
+             const double* ux, const double* uy, const double* uz, const double* theta, void* stream,
+             void* workspace, uint64_t workspace_bytes)
+{
+    if (!out) return LBM_E_ARG;
+    *out = nullptr;
+    int rc = check_boxes(boxes, nboxes, opts);
+    if (rc) return rc;
+    if (!rho || !ux || !uy || !uz || !theta) return LBM_E_ARG;
+
+    lbm_ctx* ctx = new (std::nothrow) lbm_ctx();
+    if (!ctx) return LBM_E_NOMEM;
+    ctx->storage = opts->storage;
+    ctx->newton = opts->newton_iters ? opts->newton_iters : (opts->storage == LBM_F64 ? 3 : 1);
+    ctx->rho0 = opts->rho0 > 0 ? opts->rho0 : 1.0;
+    ctx->L = plan(boxes, nboxes, opts);
+    const bool shifted = opts->storage == LBM_F16_SHIFT || opts->storage == LBM_BF16_SHIFT;
+
+    uint64_t off = 0;
+    for (int b = 0; b < nboxes; ++b) {
+        BoxDev d;
+        d.g = make_geom(uint32_t(boxes[b].nx), uint32_t(boxes[b].ny), uint32_t(boxes[b].nz));
+        d.nodes = d.g.N;
+        d.offset = off;
+        off += uint64_t(Q) * d.nodes;
+        d.omega = opts->tau_conv == LBM_TAU_LB ? 1.0 / boxes[b].tau : 2.0 / (2.0 * boxes[b].tau + 1.0);
+        ctx->boxes.push_back(d);
+    }
+
+    // domain check of the input fields (host side, before any device work)
+    const uint64_t total = ctx->L.elems / Q;
+    for (uint64_t i = 0; i < total; ++i) {
+        if (!(rho[i] > 0.0) || !(theta[i] > 0.0) || !std::isfinite(rho[i]) || !std::isfinite(theta[i]) ||
+            !std::isfinite(ux[i]) || !std::isfinite(uy[i]) || !std::isfinite(uz[i])) {
+            delete ctx;
+            return LBM_E_DOMAIN;
+        }
+    }
+
+    auto fail = [&](int code) {
+        lbm_free(ctx);
+        return code;
+    };
+
+    if (stream) {
+        ctx->stream = reinterpret_cast<hipStream_t>(stream);
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) return fail(LBM_E_HIP);
+        ctx->own_stream = true;
+    }
+    if (workspace) {
+        if (workspace_bytes < ctx->L.total || (reinterpret_cast<uintptr_t>(workspace) % ALIGN) != 0)
+            return fail(LBM_E_NOMEM);
+        ctx->mem = reinterpret_cast<char*>(workspace);
+    } else {
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&ctx->mem), ctx->L.total);
+        if (e != hipSuccess) {
+            ctx->mem = nullptr;
+            (void)hipGetLastError();
+            return fail(e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation ? LBM_E_NOMEM : LBM_E_HIP);
+        }
+        ctx->own_mem = true;
+    }
+    ctx->flag = reinterpret_cast<uint32_t*>(ctx->mem + ctx->L.flag_off);
+    ctx->partials = reinterpret_cast<double*>(ctx->mem + ctx->L.partial_off);
+    ctx->staging = ctx->mem + ctx->L.staging_off;
+
+    ctx->base.flag = ctx->flag;
+    ctx->base.xcd_remap = 1;
+    ctx->base.rho_ref = shifted ? ctx->rho0 : 0.0;
+    double e2 = 0.0;  // sum_q w_q c_q^2 rho_ref
+    for (int q = 0; q < Q; ++q)
+        e2 += SHELL_W[VEL[q].shell] * 0.25 * (VEL[q].x * VEL[q].x + VEL[q].y * VEL[q].y + VEL[q].z * VEL[q].z);
+    ctx->base.e2_ref = shifted ? e2 * ctx->rho0 : 0.0;
+    for (int s = 0; s < 6; ++s) ctx->base.wref[s] = shifted ? float(SHELL_W[s] * ctx->rho0) : 0.0f;
+    ctx->kamp = 0;
+    set_shift(ctx);
+
+    if (hipMemsetAsync(ctx->flag, 0, ALIGN, ctx->stream) != hipSuccess) return fail(LBM_E_HIP);
+    const double* fields[5] = {rho, ux, uy, uz, theta};
+
+    if (shifted) {
+        if (opts->shift_exp == LBM_SHIFT_AUTO) {
+            // largest |f - w rho0| 2^k_shell of the initial state, then k_amp
+            // so that it becomes about 2^10 (FP16 max is 65504: ~64x headroom)
+            float* maxdev = reinterpret_cast<float*>(ctx->partials);
+            if (hipMemsetAsync(maxdev, 0, sizeof(float), ctx->stream) != hipSuccess) return fail(LBM_E_HIP);
+            uint64_t base = 0;
+            for (const BoxDev& b : ctx->boxes) {
+                rc = run_init(ctx, b, base, fields, 0, maxdev);
+                if (rc) return fail(rc);
+                base += b.nodes;
+            }
+            float m = 0.f;
+            if (hipMemcpy(&m, maxdev, sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) return fail(LBM_E_HIP);
+            int k = 10;
+            if (m > 0.f && std::isfinite(m)) k = int(std::floor(std::log2(1024.0 / double(m))));
+            ctx->kamp = std::max(-40, std::min(40, k));
+        } else {
+            ctx->kamp = opts->shift_exp;
+        }
+        set_shift(ctx);
+    }
+
+    uint64_t base = 0;
+    for (const BoxDev& b : ctx->boxes) {
+        rc = run_init(ctx, b, base, fields, 1, nullptr);
+        if (rc) return fail(rc);
+        base += b.nodes;
+    }
+    uint32_t flag = 0;
+    if (hipMemcpy(&flag, ctx->flag, sizeof(flag), hipMemcpyDeviceToHost) != hipSuccess) return fail(LBM_E_HIP);
+    if (flag) return fail(LBM_E_DOMAIN);
+    *out = ctx;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* ctx, int32_t n)
+{
+    if (!ctx || n < 0) return LBM_E_ARG;
+    for (int32_t i = 0; i < n; ++i) {
+        for (const BoxDev& b : ctx->boxes) {
+            int rc = launch_step(ctx, b);
+            if (rc) return rc;
+        }
+        ctx->cur ^= 1;
+    }
+    return LBM_OK;
+}
+
+int lbm_synchronize(lbm_ctx* ctx)
+{
+    if (!ctx) return LBM_E_ARG;
+    return hipStreamSynchronize(ctx->stream) == hipSuccess ? LBM_OK : LBM_E_HIP;
+}
+
+int lbm_moments(lbm_ctx* ctx, double* rho, double* jx, double* jy, double* jz, double* energy)
+{
+    if (!ctx) return LBM_E_ARG;
+    double* outs[5] = {rho, jx, jy, jz, energy};
+    const uint64_t chunk = ctx->L.staging_bytes / (5 * sizeof(double));
+    double* stage = reinterpret_cast<double*>(ctx->staging);
+    uint64_t base = 0;
+    for (const BoxDev& b : ctx->boxes) {
+        const StepParams p = ctx->params(b);
+        for (uint64_t n0 = 0; n0 < b.nodes; n0 += chunk) {
+            const uint64_t cnt = std::min(chunk, b.nodes - n0);
+            int rc = dispatch_storage(ctx->storage, [&](auto st) {
+                using ST = decltype(st);
+                using T = typename ST::T;
+                const T* f = reinterpret_cast<const T*>(ctx->buf(ctx->cur)) + b.offset;
+                hipLaunchKernelGGL((k_moments<ST>), dim3(nblocks(cnt)), dim3(BLOCK), 0, ctx->stream, f,
+                                   uint32_t(b.nodes), uint32_t(n0), uint32_t(cnt), p, stage);
+                return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+            });
+            if (rc) return rc;
+            for (int k = 0; k < 5; ++k)
+                if (outs[k])
+                    HIPCHK(hipMemcpyAsync(outs[k] + base + n0, stage + k * cnt, cnt * sizeof(double),
+                                          hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+        }
+        base += b.nodes;
+    }
+    return LBM_OK;
+}
+
+int lbm_status(lbm_ctx* ctx)
+{
+    if (!ctx) return LBM_E_ARG;
+    uint32_t flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, ctx->flag, sizeof(flag), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return flag ? LBM_E_NONFINITE : LBM_OK;
+}
+
+int lbm_totals(lbm_ctx* ctx, double* out)
+{
+    if (!ctx || !out) return LBM_E_ARG;
+    double* res = ctx->partials + TOTAL_BLOCKS * 5;
+    for (size_t bi = 0; bi < ctx->boxes.size(); ++bi) {
+        const BoxDev& b = ctx->boxes[bi];
+        const StepParams p = ctx->params(b);
+        const uint32_t nblk = std::min<uint32_t>(TOTAL_BLOCKS, nblocks(b.nodes));
+        int rc = dispatch_storage(ctx->storage, [&](auto st) {
+            using ST = decltype(st);
+            using T = typename ST::T;
+            const T* f = reinterpret_cast<const T*>(ctx->buf(ctx->cur)) + b.offset;
+            hipLaunchKernelGGL((k_totals<ST>), dim3(nblk), dim3(BLOCK), 0, ctx->stream, f, uint32_t(b.nodes), p,
+                               ctx->partials);
+            hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->partials, nblk, res);
+            return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+        });
+        if (rc) return rc;
+        HIPCHK(hipMemcpyAsync(out + 5 * bi, res, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return lbm_status(ctx);
+}
+
+int lbm_get_populations(lbm_ctx* ctx, double* f)
+{
+    if (!ctx || !f) return LBM_E_ARG;
+    const uint64_t chunk = ctx->L.staging_bytes / sizeof(double);
+    double* stage = reinterpret_cast<double*>(ctx->staging);
+    uint64_t host_off = 0;
+    for (const BoxDev& b : ctx->boxes) {
+        for (int q = 0; q < Q; ++q) {
+            const int sh = VEL[q].shell;
+            for (uint64_t n0 = 0; n0 < b.nodes; n0 += chunk) {
+                const uint64_t cnt = std::min(chunk, b.nodes - n0);
+                int rc = dispatch_storage(ctx->storage, [&](auto st) {
+                    using ST = decltype(st);
+                    using T = typename ST::T;
+                    const T* fq = reinterpret_cast<const T*>(ctx->buf(ctx->cur)) + b.offset + uint64_t(q) * b.nodes + n0;
+                    hipLaunchKernelGGL((k_get<ST>), dim3(nblocks(cnt)), dim3(BLOCK), 0, ctx->stream, fq,
+                                       uint32_t(cnt), ctx->base.inv_scale[sh], SHELL_W[sh] * ctx->base.rho_ref, stage);
+                    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+                });
+                if (rc) return rc;
+                HIPCHK(hipMemcpyAsync(f + host_off + uint64_t(q) * b.nodes + n0, stage, cnt * sizeof(double),
+                                      hipMemcpyDeviceToHost, ctx->stream));
+                HIPCHK(hipStreamSynchronize(ctx->stream));
+            }
+        }
+        host_off += uint64_t(Q) * b.nodes;
+    }
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx* ctx, const double* f)
+{
+    if (!ctx || !f) return LBM_E_ARG;
+    const uint64_t chunk = ctx->L.staging_bytes / sizeof(double);
+    double* stage = reinterpret_cast<double*>(ctx->staging);
+    uint64_t host_off = 0;
+    for (const BoxDev& b : ctx->boxes) {
+        for (int q = 0; q < Q; ++q) {
+            const int sh = VEL[q].shell;
+            for (uint64_t n0 = 0; n0 < b.nodes; n0 += chunk) {
+                const uint64_t cnt = std::min(chunk, b.nodes - n0);
+                HIPCHK(hipMemcpyAsync(stage, f + host_off + uint64_t(q) * b.nodes + n0, cnt * sizeof(double),
+                                      hipMemcpyHostToDevice, ctx->stream));
+                int rc = dispatch_storage(ctx->storage, [&](auto st) {
+                    using ST = decltype(st);
+                    using T = typename ST::T;
+                    T* fq = reinterpret_cast<T*>(ctx->buf(ctx->cur)) + b.offset + uint64_t(q) * b.nodes + n0;
+                    hipLaunchKernelGGL((k_set<ST>), dim3(nblocks(cnt)), dim3(BLOCK), 0, ctx->stream, fq,
+                                       uint32_t(cnt), ctx->base.scale[sh], SHELL_W[sh] * ctx->base.rho_ref, stage);
+                    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+                });
+                if (rc) return rc;
+                HIPCHK(hipStreamSynchronize(ctx->stream));
+            }
+        }
+        host_off += uint64_t(Q) * b.nodes;
+    }
+    return LBM_OK;
+}
+
+int lbm_gather(lbm_ctx* ctx, int32_t box, const int64_t* idx, int64_t count, double* out)
+{
+    if (!ctx || box < 0 || box >= int32_t(ctx->boxes.size()) || count < 0) return LBM_E_ARG;
+    if (count == 0) return LBM_OK;
+    if (!idx || !out) return LBM_E_ARG;
+    const BoxDev& b = ctx->boxes[box];
+    const int64_t lim = int64_t(Q) * int64_t(b.nodes);
+    for (int64_t i = 0; i < count; ++i)
+        if (idx[i] < 0 || idx[i] >= lim) return LBM_E_ARG;
+    const uint64_t chunk = ctx->L.staging_bytes / (2 * sizeof(double));
+    int64_t* sidx = reinterpret_cast<int64_t*>(ctx->staging);
+    double* sout = reinterpret_cast<double*>(ctx->staging + chunk * sizeof(int64_t));
+    const StepParams p = ctx->params(b);
+    for (int64_t i0 = 0; i0 < count; i0 += int64_t(chunk)) {
+        const uint64_t cnt = std::min<uint64_t>(chunk, uint64_t(count - i0));
+        HIPCHK(hipMemcpyAsync(sidx, idx + i0, cnt * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+        int rc = dispatch_storage(ctx->storage, [&](auto st) {
+            using ST = decltype(st);
+            using T = typename ST::T;
+            const T* f = reinterpret_cast<const T*>(ctx->buf(ctx->cur)) + b.offset;
+            hipLaunchKernelGGL((k_gather<ST>), dim3(nblocks(cnt)), dim3(BLOCK), 0, ctx->stream, f, uint32_t(b.nodes),
+                               sidx, uint32_t(cnt), p, sout);
+            return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+        });
+        if (rc) return rc;
+        HIPCHK(hipMemcpyAsync(out + i0, sout, cnt * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return LBM_OK;
+}
+
+int lbm_debug_pull_map(lbm_ctx* ctx, int32_t box, int64_t* src)
+{
+    if (!ctx || !src || box < 0 || box >= int32_t(ctx->boxes.size())) return LBM_E_ARG;
+    const BoxDev& b = ctx->boxes[box];
+    const uint64_t chunk = ctx->L.staging_bytes / (uint64_t(Q) * sizeof(int64_t));
+    int64_t* stage = reinterpret_cast<int64_t*>(ctx->staging);
+    for (uint64_t n0 = 0; n0 < b.nodes; n0 += chunk) {
+        const uint64_t cnt = std::min(chunk, b.nodes - n0);
+        hipLaunchKernelGGL(k_pull_map, dim3(nblocks(cnt)), dim3(BLOCK), 0, ctx->stream, b.g, uint32_t(n0),
+                           uint32_t(cnt), stage);
+        HIPCHK(hipGetLastError());
+        for (int q = 0; q < Q; ++q)
+            HIPCHK(hipMemcpyAsync(src + uint64_t(q) * b.nodes + n0, stage + uint64_t(q) * cnt, cnt * sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return LBM_OK;
+}
+
+int lbm_get_info(lbm_ctx* ctx, lbm_info* info)
+{
+    if (!ctx || !info) return LBM_E_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->storage = ctx->storage;
+    info->newton_iters = ctx->newton;
+    info->shift_exp = (ctx->storage == LBM_F16_SHIFT || ctx->storage == LBM_BF16_SHIFT) ? ctx->kamp : 0;
+    info->nboxes = int32_t(ctx->boxes.size());
+    info->nodes = int64_t(ctx->L.elems / Q);
+    info->bytes_per_step = int64_t(2 * ctx->L.elems * uint64_t(elem_bytes(ctx->storage)));
+    info->block_threads = ctx->block_threads;
+    info->variant = ctx->variant;
+    info->device_bytes = ctx->L.total;
+    return LBM_OK;
+}
+
+void* lbm_stream(lbm_ctx* ctx) { return ctx ? reinterpret_cast<void*>(ctx->stream) : nullptr; }
+
+void lbm_free(lbm_ctx* ctx)
+{
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->own_mem && ctx->mem) (void)hipFree(ctx->mem);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char* lbm_strerror(int code)
+{
+    switch (code) {
+        case LBM_OK: return "ok";
+        case LBM_E_ARG: return "invalid argument";
+        case LBM_E_NOMEM: return "out of memory (or workspace too small)";
+        case LBM_E_DOMAIN: return "unrealisable input state (rho <= 0, theta <= 0 or non-finite)";
+        case LBM_E_NONFINITE: return "a step produced a non-finite or unrealisable node";
+        case LBM_E_HIP: return "HIP runtime error";
+        case LBM_E_UNSUPPORTED: return "unsupported request";
+        default: return "unknown error";
+    }
+}
+
+int lbm_selftest(void)
+{
+    // division by invariant integers: all small divisors on a spread of n,
+    // plus the extremes of the 32-bit range
+    uint64_t state = 0x9e3779b97f4a7c15ull;
+    for (uint32_t d = 1; d <= 4096; ++d) {
+        const FastDiv f = make_fastdiv(d);
+        for (int i = 0; i < 256; ++i) {
+            state = state * 6364136223846793005ull + 1442695040888963407ull;
+            const uint32_t n = i < 4 ? (i == 0 ? 0u : i == 1 ? 0xffffffffu : i == 2 ? d - 1 : d) : uint32_t(state >> 32);
+            if (fdiv(n, f) != n / d) return LBM_E_ARG;
+        }
+    }
+    for (uint32_t d : {1000003u, 1u << 20, (1u << 31) + 7u, 0xffffffffu}) {
+        const FastDiv f = make_fastdiv(d);
+        for (uint32_t n : {0u, d - 1, d, 2 * d - 1, 0xfffffffeu, 0xffffffffu})
+            if (fdiv(n, f) != n / d) return LBM_E_ARG;
+    }
+    return LBM_OK;
+}
+
+}  // extern "C"

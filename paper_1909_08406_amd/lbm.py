@@ -1,0 +1,247 @@
+"""ctypes binding of liblbm.so (declared in include/lbm.h).
+
+Argument marshalling only: every step of the update runs in the HIP
+library. PyTorch supplies device memory (the context workspace) and the
+stream. If the built library is missing this module raises at import
+time; there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+NQ = 41
+F64, F32, F16_SHIFT, BF16_SHIFT = 0, 1, 2, 3
+TAU_LB, TAU_PAPER = 0, 1
+SHIFT_AUTO = -1000
+STORAGE = {"f64": F64, "f32": F32, "f16s": F16_SHIFT, "bf16s": BF16_SHIFT}
+
+OK, E_ARG, E_NOMEM, E_DOMAIN, E_NONFINITE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, lib().lbm_strerror(code).decode(), code))
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tau", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("storage", ctypes.c_int32), ("tau_conv", ctypes.c_int32), ("rho0", ctypes.c_double),
+                ("newton_iters", ctypes.c_int32), ("shift_exp", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("storage", ctypes.c_int32), ("newton_iters", ctypes.c_int32), ("shift_exp", ctypes.c_int32),
+                ("nboxes", ctypes.c_int32), ("nodes", ctypes.c_int64), ("bytes_per_step", ctypes.c_int64),
+                ("block_threads", ctypes.c_int32), ("variant", ctypes.c_int32), ("device_bytes", ctypes.c_uint64)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_lp = ctypes.POINTER(ctypes.c_int64)
+_vp = ctypes.c_void_p
+
+# every symbol of include/lbm.h with its C signature
+SIGNATURES = {
+    "lbm_lattice": (ctypes.c_int, [_dp, _dp, _dp]),
+    "lbm_workspace_size": (ctypes.c_int, [ctypes.POINTER(Box), ctypes.c_int32, ctypes.POINTER(Opts),
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "lbm_init": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(Box), ctypes.c_int32, ctypes.POINTER(Opts),
+                                _dp, _dp, _dp, _dp, _dp, _vp, _vp, ctypes.c_uint64]),
+    "lbm_step": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "lbm_synchronize": (ctypes.c_int, [_vp]),
+    "lbm_moments": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
+    "lbm_totals": (ctypes.c_int, [_vp, _dp]),
+    "lbm_status": (ctypes.c_int, [_vp]),
+    "lbm_get_populations": (ctypes.c_int, [_vp, _dp]),
+    "lbm_set_populations": (ctypes.c_int, [_vp, _dp]),
+    "lbm_gather": (ctypes.c_int, [_vp, ctypes.c_int32, _lp, ctypes.c_int64, _dp]),
+    "lbm_debug_pull_map": (ctypes.c_int, [_vp, ctypes.c_int32, _lp]),
+    "lbm_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
+    "lbm_stream": (_vp, [_vp]),
+    "lbm_free": (None, [_vp]),
+    "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "lbm_selftest": (ctypes.c_int, []),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblbm.so is not built (run __graft_entry__.build()); "
+                              "the GPU path has no fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise LbmError(rc, what)
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def lattice():
+    """(c[41,3], w[41], theta0) as the library holds them."""
+    c = np.zeros((NQ, 3))
+    w = np.zeros(NQ)
+    t = np.zeros(1)
+    _check(lib().lbm_lattice(_d(c), _d(w), _d(t)), "lbm_lattice")
+    return c, w, float(t[0])
+
+
+def _boxes(boxes):
+    arr = (Box * len(boxes))()
+    for i, b in enumerate(boxes):
+        nx, ny, nz, tau = b
+        arr[i] = Box(int(nx), int(ny), int(nz), 0, float(tau))
+    return arr
+
+
+def _opts(storage, tau_conv, rho0, newton_iters, shift_exp):
+    st = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    return Opts(st, int(tau_conv), float(rho0), int(newton_iters),
+                SHIFT_AUTO if shift_exp is None else int(shift_exp), 0, 0)
+
+
+def workspace_size(boxes, storage="f32", tau_conv=TAU_LB, rho0=1.0, newton_iters=0, shift_exp=None):
+    bx = _boxes(boxes)
+    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp)
+    out = ctypes.c_uint64(0)
+    _check(lib().lbm_workspace_size(bx, len(boxes), ctypes.byref(op), ctypes.byref(out)), "lbm_workspace_size")
+    return int(out.value)
+
+
+class Context:
+    """A live lbm_ctx. Methods are the C entry points without the prefix."""
+
+    def __init__(self, handle, boxes, workspace, stream):
+        self._h = handle
+        self.boxes = [tuple(b) for b in boxes]
+        self._workspace = workspace  # keeps the torch allocation alive
+        self._stream = stream
+        self.box_nodes = [2 * b[0] * b[1] * b[2] for b in self.boxes]
+        self.nodes = sum(self.box_nodes)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("context already freed")
+        return self._h
+
+    def step(self, n=1):
+        _check(lib().lbm_step(self.handle, int(n)), "lbm_step")
+
+    def synchronize(self):
+        _check(lib().lbm_synchronize(self.handle), "lbm_synchronize")
+
+    def moments(self):
+        """(5, nodes) array: rho, jx, jy, jz, E per node (FP64)."""
+        m = np.zeros((5, self.nodes))
+        _check(lib().lbm_moments(self.handle, *[_d(m[k]) for k in range(5)]), "lbm_moments")
+        return m
+
+    def totals(self, check=True):
+        """(nboxes, 5): mass, Jx, Jy, Jz, E per box, summed in FP64 on the device."""
+        out = np.zeros((len(self.boxes), 5))
+        rc = lib().lbm_totals(self.handle, _d(out))
+        if check:
+            _check(rc, "lbm_totals")
+        return out
+
+    def status(self):
+        return int(lib().lbm_status(self.handle))
+
+    def get_populations(self):
+        f = np.zeros(NQ * self.nodes)
+        _check(lib().lbm_get_populations(self.handle, _d(f)), "lbm_get_populations")
+        return f
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        if f.size != NQ * self.nodes:
+            raise ValueError("expected %d values" % (NQ * self.nodes))
+        _check(lib().lbm_set_populations(self.handle, _d(f)), "lbm_set_populations")
+
+    def gather(self, box, idx):
+        idx = np.ascontiguousarray(idx, dtype=np.int64).reshape(-1)
+        out = np.zeros(idx.size)
+        _check(lib().lbm_gather(self.handle, int(box), idx.ctypes.data_as(_lp), idx.size, _d(out)), "lbm_gather")
+        return out
+
+    def debug_pull_map(self, box=0):
+        n = self.box_nodes[box]
+        out = np.zeros(NQ * n, dtype=np.int64)
+        _check(lib().lbm_debug_pull_map(self.handle, int(box), out.ctypes.data_as(_lp)), "lbm_debug_pull_map")
+        return out.reshape(NQ, n)
+
+    def info(self):
+        i = Info()
+        _check(lib().lbm_get_info(self.handle, ctypes.byref(i)), "lbm_get_info")
+        return {k: getattr(i, k) for k, _ in Info._fields_}
+
+    def stream(self):
+        return lib().lbm_stream(self.handle)
+
+    def free(self):
+        if self._h is not None:
+            lib().lbm_free(self._h)
+            self._h = None
+            self._workspace = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def init(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0, newton_iters=0,
+         shift_exp=None, stream=None, torch_workspace=True):
+    """lbm_init. boxes: [(nx, ny, nz, tau), ...]; nodal FP64 fields of all
+    boxes concatenated (theta absolute). stream: a torch.cuda.Stream (or
+    None for the library's own). With torch_workspace the device memory is a
+    torch uint8 tensor held by the returned Context."""
+    bx = _boxes(boxes)
+    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (rho, ux, uy, uz, theta)]
+    nodes = sum(2 * b[0] * b[1] * b[2] for b in boxes)
+    for a in arrs:
+        if a.size != nodes:
+            raise ValueError("field has %d values, boxes have %d nodes" % (a.size, nodes))
+    ws = None
+    ws_ptr, ws_bytes = None, 0
+    if torch_workspace:
+        import torch
+        ws_bytes = workspace_size(boxes, storage, tau_conv, rho0, newton_iters, shift_exp)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        ws_ptr = ws.data_ptr()
+    sptr = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    h = _vp()
+    rc = lib().lbm_init(ctypes.byref(h), bx, len(boxes), ctypes.byref(op), *[_d(a) for a in arrs], sptr,
+                        ws_ptr, ws_bytes)
+    _check(rc, "lbm_init")
+    return Context(h, boxes, ws, stream)
+
+
+def selftest():
+    return int(lib().lbm_selftest())

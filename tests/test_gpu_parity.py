@@ -1,0 +1,284 @@
+"""Parity of the HIP path (through the C-ABI) against the FP64 CPU oracle.
+
+Bars: integer streaming maps bit-exact; moments after the run within 1e-12
+relative (FP64) and 1e-5 relative (FP32), where the relative error of a
+field m is max|m_gpu - m_ref| / max|m_ref| over nodes.
+
+The GPU holds post-collision populations (pull scheme) while the oracle
+holds pre-collision ones (collide then push); their conserved moments are
+equal, and the oracle's collide_field() of its state gives the GPU's
+populations, which are compared element by element.
+"""
+import numpy as np
+import pytest
+
+from paper_1909_08406_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    from paper_1909_08406_amd import lbm
+    return lbm
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def moment_errors(m_gpu, m_ref):
+    return [rel_err(m_gpu[k], m_ref[k]) if np.max(np.abs(m_ref[k])) > 0 else float(np.max(np.abs(m_gpu[k])))
+            for k in range(5)]
+
+
+def oracle_run(orc, dims, tau, F, steps):
+    nx, ny, nz = dims
+    _, _, th = orc.lattice()
+    f = orc.init(nx, ny, nz, *F.absolute(th))
+    return orc.run(nx, ny, nz, 1.0 / tau, f, steps)
+
+
+def gpu_run(L, dims, tau, F, steps, storage, **kw):
+    _, _, th = L.lattice()
+    ctx = L.init([(*dims, tau)], *F.absolute(th), storage=storage, **kw)
+    ctx.step(steps)
+    return ctx
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 2, 2), (3, 2, 1), (5, 7, 3), (17, 9, 5), (32, 16, 16)])
+def test_pull_map_bit_exact(L, orc, dims):
+    say("pull map", dims)
+    F = wl.standing_wave(*dims, amp=0.0)
+    ctx = gpu_run(L, dims, 0.6, F, 0, "f32")
+    got = ctx.debug_pull_map(0)
+    ctx.free()
+    assert np.array_equal(got, orc.pull_map(*dims))
+
+
+def test_init_equilibrium_matches_oracle(L, orc):
+    """The closed-form partition-function Newton (GPU) and the generic 5x5
+    Newton (oracle) give the same entropic equilibrium, up to Ma ~ 0.4."""
+    dims = (7, 5, 3)
+    say("init equilibrium", dims)
+    F = wl.random_state(*dims, seed=21, amp_rho=0.2, amp_u=0.25, amp_theta=0.1)
+    ctx = gpu_run(L, dims, 0.6, F, 0, "f64")
+    g = ctx.get_populations().reshape(41, -1)
+    ctx.free()
+    _, _, th = orc.lattice()
+    f = orc.init(*dims, *F.absolute(th))
+    assert np.max(np.abs(g - f)) < 2e-15
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_standing_wave_32x16x16_200_steps(L, orc, storage, tol):
+    """Plain method on a 32x16x16 box, rho = 1 + 1e-3 sin(2 pi x/32),
+    tau = 0.6, 200 steps."""
+    dims, tau, steps = (32, 16, 16), 0.6, 200
+    say("standing wave", storage, dims, steps)
+    F = wl.standing_wave(*dims, amp=1e-3)
+    ctx = gpu_run(L, dims, tau, F, steps, storage)
+    m_gpu = ctx.moments()
+    g = ctx.get_populations().reshape(41, -1)
+    ctx.free()
+    f = oracle_run(orc, dims, tau, F, steps)
+    m_ref = orc.moment_fields(f)
+    errs = moment_errors(m_gpu, m_ref)
+    say("  moment errors", ["%.2e" % e for e in errs])
+    assert max(errs) <= tol
+    # fluctuation error relative to the wave amplitude (stricter)
+    drho = rel_err(m_gpu[0] - 1.0, m_ref[0] - 1.0)
+    say("  density-fluctuation error %.2e" % drho)
+    assert drho <= (1e-9 if storage == "f64" else 2e-3)
+    g_ref = orc.collide_field(*dims, 1.0 / tau, f)
+    perr = rel_err(g, g_ref)
+    say("  population error %.2e" % perr)
+    assert perr <= tol
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+@pytest.mark.parametrize("amp_u", [0.05, 0.2])
+def test_random_state_ragged_box(L, orc, storage, tol, amp_u):
+    """Independent random nodes (up to |u| ~ 0.35, i.e. Ma ~ 0.5) on a
+    13x7x5 box: 910 nodes, four tiles of 256 and a ragged tail."""
+    dims, tau, steps = (13, 7, 5), 0.55, 30
+    say("random state", storage, amp_u, dims)
+    F = wl.random_state(*dims, seed=5, amp_u=amp_u)
+    ctx = gpu_run(L, dims, tau, F, steps, storage)
+    m_gpu = ctx.moments()
+    g = ctx.get_populations().reshape(41, -1)
+    assert ctx.status() == 0
+    ctx.free()
+    f = oracle_run(orc, dims, tau, F, steps)
+    errs = moment_errors(m_gpu, orc.moment_fields(f))
+    say("  moment errors", ["%.2e" % e for e in errs])
+    assert max(errs) <= tol
+    assert rel_err(g, orc.collide_field(*dims, 1.0 / tau, f)) <= tol
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_several_boxes_in_one_context(L, orc, storage):
+    boxes = [(5, 3, 2, 0.6), (8, 4, 4, 0.7), (3, 3, 3, 0.95), (1, 2, 3, 0.52)]
+    say("multi-box", storage, boxes)
+    _, _, th = L.lattice()
+    fields = [wl.random_state(b[0], b[1], b[2], seed=30 + i) for i, b in enumerate(boxes)]
+    cat = wl.concat(fields)
+    ctx = L.init(boxes, cat[0], cat[1], cat[2], cat[3], cat[4] * th, storage=storage)
+    ctx.step(12)
+    m = ctx.moments()
+    tot = ctx.totals()
+    ctx.free()
+    tol = 1e-12 if storage == "f64" else 1e-5
+    off = 0
+    for i, (b, F) in enumerate(zip(boxes, fields)):
+        n = 2 * b[0] * b[1] * b[2]
+        f = oracle_run(orc, b[:3], b[3], F, 12)
+        m_ref = orc.moment_fields(f)
+        assert max(moment_errors(m[:, off:off + n], m_ref)) <= tol, i
+        t_ref = orc.totals(f)
+        assert abs(tot[i, 0] / t_ref[0] - 1) <= tol and abs(tot[i, 4] / t_ref[4] - 1) <= tol
+        off += n
+
+
+def test_fp64_conservation_and_totals(L, orc):
+    """Exact conservation of mass, momentum and energy (Sec. V) shows as
+    global FP64 totals that drift only by rounding over 200 steps."""
+    dims, tau = (32, 16, 16), 0.6
+    say("conservation fp64", dims)
+    F = wl.random_state(*dims, seed=3, amp_u=0.05)
+    _, _, th = L.lattice()
+    ctx = L.init([(*dims, tau)], *F.absolute(th), storage="f64")
+    t0 = ctx.totals()[0]
+    ctx.step(200)
+    t1 = ctx.totals()[0]
+    ctx.free()
+    scale = np.array([t0[0]] * 4 + [t0[4]])
+    drift = np.abs(t1 - t0) / scale
+    say("  drift", drift)
+    assert np.max(drift) < 1e-13
+    _, _, tho = orc.lattice()
+    f = orc.init(*dims, *F.absolute(tho))
+    ref = orc.totals(f)
+    assert np.max(np.abs(t0 - ref) / scale) < 1e-13
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
+def test_checkpoint_resume_is_bit_identical(L, storage):
+    dims, tau = (9, 6, 4), 0.58
+    say("checkpoint", storage)
+    F = wl.random_state(*dims, seed=12, amp_u=0.03, amp_rho=1e-3, amp_theta=1e-3)
+    _, _, th = L.lattice()
+    a = L.init([(*dims, tau)], *F.absolute(th), storage=storage)
+    a.step(10)
+    ref = a.get_populations()
+    a.free()
+    b = L.init([(*dims, tau)], *F.absolute(th), storage=storage)
+    b.step(4)
+    snap = b.get_populations()
+    b.free()
+    c = L.init([(*dims, tau)], *F.absolute(th), storage=storage)
+    c.set_populations(snap)
+    c.step(6)
+    got = c.get_populations()
+    c.free()
+    assert np.array_equal(got, ref)
+
+
+def test_uniform_equilibrium_fixed_point(L):
+    dims = (6, 5, 4)
+    n = 2 * 6 * 5 * 4
+    one = np.ones(n)
+    _, _, th = L.lattice()
+    for storage, tol in (("f64", 4e-16), ("f32", 2e-7)):
+        ctx = L.init([(*dims, 0.6)], 1.1 * one, 0.02 * one, -0.01 * one, 0.005 * one, 1.01 * th * one,
+                     storage=storage)
+        f0 = ctx.get_populations()
+        ctx.step(10)
+        f1 = ctx.get_populations()
+        ctx.free()
+        assert np.max(np.abs(f1 - f0)) <= tol * np.max(f0), storage
+
+
+def test_nonfinite_state_is_flagged(L):
+    """Unrealisable populations set from the host make the step flag the
+    node; the kernel itself completes normally."""
+    dims = (4, 4, 4)
+    F = wl.standing_wave(*dims, amp=0.0)
+    _, _, th = L.lattice()
+    ctx = L.init([(*dims, 0.6)], *F.absolute(th), storage="f32")
+    assert ctx.status() == 0
+    f = ctx.get_populations().reshape(41, -1)
+    f[:, 0] = -f[:, 0]  # node 0: negative density
+    ctx.set_populations(f)
+    ctx.step(1)
+    assert ctx.status() == L.E_NONFINITE
+    with pytest.raises(L.LbmError) as e:
+        ctx.totals()
+    assert e.value.code == L.E_NONFINITE
+    ctx.free()
+
+
+@pytest.mark.parametrize("storage", ["f16s", "bf16s"])
+def test_shifted_storage_error_vs_fp64(L, orc, storage):
+    """Shifted 16-bit storage of f - w rho0 with FP32 arithmetic, against the
+    FP64 oracle on the 32x16x16 standing wave after 200 steps."""
+    dims, tau, steps = (32, 16, 16), 0.6, 200
+    F = wl.standing_wave(*dims, amp=1e-3)
+    ctx = gpu_run(L, dims, tau, F, steps, storage)
+    info = ctx.info()
+    m_gpu = ctx.moments()
+    ctx.free()
+    f = oracle_run(orc, dims, tau, F, steps)
+    m_ref = orc.moment_fields(f)
+    errs = moment_errors(m_gpu, m_ref)
+    drho = rel_err(m_gpu[0] - 1.0, m_ref[0] - 1.0)
+    say("shifted", storage, "k_amp", info["shift_exp"], "moment errors", ["%.2e" % e for e in errs],
+        "density-fluctuation error %.2e" % drho)
+    assert max(errs) <= 1e-5
+    assert drho <= (2e-2 if storage == "f16s" else 1e-1)
+
+
+def _sampled_step_check(L, orc, dims, tau, F, storage, warm, nsample, tol, seed=0):
+    """At full size: after `warm` steps, compute one more step for sampled
+    nodes with the oracle (pull by the oracle's own map, then collide) from
+    the GPU's held state, and compare with the GPU's next state."""
+    _, _, th = L.lattice()
+    ctx = L.init([(*dims, tau)], *F.absolute(th), storage=storage)
+    ctx.step(warm)
+    N = 2 * dims[0] * dims[1] * dims[2]
+    rng = np.random.default_rng(seed)
+    nodes = np.concatenate([[0, N - 1, N // 2 - 1, N // 2], rng.integers(0, N, nsample)]).astype(np.int64)
+    src = orc.pull_sources(*dims, nodes)                       # [k, 41]
+    q = np.arange(41, dtype=np.int64)
+    pulled = ctx.gather(0, (q[None, :] * N + src).reshape(-1)).reshape(-1, 41)
+    ctx.step(1)
+    got = ctx.gather(0, (q[None, :] * N + nodes[:, None]).reshape(-1)).reshape(-1, 41)
+    status = ctx.status()
+    ctx.free()
+    ref = np.stack([orc.collide_node(p, 1.0 / tau) for p in pulled])
+    err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    say("  sampled step error %.2e over %d nodes" % (err, nodes.size))
+    assert status == 0
+    assert err <= tol
+
+
+def test_sampled_full_size_thermal_mode_128(L, orc):
+    """Plain method, FP32, 128^3 thermal mode with seeded density noise."""
+    say("sampled 128^3 fp32")
+    F = wl.thermal_mode(128)
+    _sampled_step_check(L, orc, (128, 128, 128), 0.55, F, "f32", 5, 2000, 2e-6)
+
+
+def test_sampled_full_size_taylor_green_256(L, orc):
+    """Plain method, FP32, 256^3 Taylor-Green vortex at Ma = 0.3."""
+    say("sampled 256^3 fp32 TGV")
+    _, _, th = L.lattice()
+    F = wl.taylor_green(256, 0.3 * np.sqrt(5.0 / 3.0 * th))
+    _sampled_step_check(L, orc, (256, 256, 256), 0.51816, F, "f32", 3, 2000, 2e-6)
