@@ -31,9 +31,29 @@ def parse():
     ap.add_argument("--storages", default="f16s,f32", help="first one is the headline")
     ap.add_argument("--tau", type=float, default=0.6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=64, help="cells per edge of the oracle sample")
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-n", type=int, default=128, help="cells per edge of the oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--copy-reference", type=float, default=0.0, metavar="GIB",
+                    help="only time a plain device-to-device copy of GIB GiB (HBM counter reference)")
     return ap.parse_args()
+
+
+def copy_reference(torch, gib, reps=5):
+    """A plain copy kernel of known size: bytes read = bytes written = GIB GiB."""
+    n = int(gib * (1 << 30))
+    a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    e.synchronize()
+    ms = s.elapsed_time(e) / reps
+    print(json.dumps({"copy_reference_bytes_read": n, "copy_reference_bytes_written": n, "ms": ms,
+                      "gbs_read_plus_write": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def time_storage(lbm, torch, F, th, n, tau, storage, steps, warmup):
@@ -113,6 +133,9 @@ def main():
     from paper_1909_08406_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.copy_reference > 0:
+        copy_reference(torch, args.copy_reference)
+        return
     _, _, th = lbm.lattice()
     n = args.n
     t0 = time.time()

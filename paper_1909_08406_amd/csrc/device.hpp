@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 
 #include "lattice.hpp"
 
@@ -85,12 +86,13 @@ __device__ inline Coord decode(uint32_t n, const Geom& g)
     return c;
 }
 
-// Wrapped neighbour offsets of one node. For an integer move by d in
-// [-2, 2] along an axis the source coordinate is (x - d) mod n, held in
-// o[2 - d]... i.e. o[k] = (x + k - 2) mod n scaled by the axis stride. The
-// half moves sigma/2 (sigma = +-1) connect the sublattices: a node at
-// x + s/2 receives from the other sublattice at x + s - (1 + sigma)/2, held
-// in h[0] for sigma = +1 and h[1] for sigma = -1.
+// Wrapped neighbour offsets of one node, scaled by `unit` (1 for node ids,
+// sizeof(element) for byte offsets into a q-block). For an integer move by d
+// in [-2, 2] along an axis the source coordinate is (x - d) mod n, held in
+// o[2 - d]; i.e. o[k] = ((x + k - 2) mod n) * stride. The half moves sigma/2
+// (sigma = +-1) connect the sublattices: a node at x + s/2 receives from the
+// other sublattice at x + s - (1 + sigma)/2, held in h[0] for sigma = +1 and
+// h[1] for sigma = -1.
 struct Nbr {
     uint32_t xo[5], yo[5], zo[5];
     uint32_t xh[2], yh[2], zh[2];
@@ -112,17 +114,17 @@ __device__ inline void axis_wrap(uint32_t x, uint32_t n, uint32_t stride, uint32
     h[1] = s ? o[3] : o[2];
 }
 
-__device__ inline void make_nbr(const Geom& g, const Coord& c, Nbr& nb)
+__device__ inline void make_nbr(const Geom& g, const Coord& c, Nbr& nb, uint32_t unit = 1)
 {
-    axis_wrap(c.x, g.nx, 1, c.s, nb.xo, nb.xh);
-    axis_wrap(c.y, g.ny, g.nx, c.s, nb.yo, nb.yh);
-    axis_wrap(c.z, g.nz, g.nxy, c.s, nb.zo, nb.zh);
-    nb.so = c.s ? g.plane : 0;
-    nb.sh = c.s ? 0 : g.plane;
+    axis_wrap(c.x, g.nx, unit, c.s, nb.xo, nb.xh);
+    axis_wrap(c.y, g.ny, g.nx * unit, c.s, nb.yo, nb.yh);
+    axis_wrap(c.z, g.nz, g.nxy * unit, c.s, nb.zo, nb.zh);
+    nb.so = c.s ? g.plane * unit : 0;
+    nb.sh = c.s ? 0 : g.plane * unit;
 }
 
-// Node that population q is pulled from (Sec. IV: streaming along the links
-// of the bcc lattice, periodic wrap).
+// Offset (in the unit of make_nbr) of the node that population q is pulled
+// from (Sec. IV: streaming along the links of the bcc lattice, periodic).
 template <int q>
 __device__ inline uint32_t pull_src(const Nbr& nb)
 {
@@ -254,46 +256,138 @@ __device__ inline void newton_step(Mult<R>& m, R ux, R uy, R uz, R K)
     m.g -= x3;
 }
 
-// w_q e^{b.c_q - g c_q^2} for all q, and their sum Z.
+// Factors of the Gibbs terms w_q e^{b.c_q - g c_q^2}: per-axis powers
+// e^{+-b/2}, e^{+-b}, e^{+-2b}, the shell prefactors w_s t^{4 |c_s|^2}
+// (t = e^{-g/4}) and Z = sum_q w_q e^{...} in closed form over the shells.
 template <typename R>
-__device__ inline void gibbs_terms(const Mult<R>& m, R e[Q], R& Z)
-{
+struct Gibbs {
     R p1[3], m1[3], p2[3], m2[3], p4[3], m4[3];
+    R T[6];
+    R Z;
+};
+
+template <typename R>
+__device__ inline void gibbs_factors(const Mult<R>& m, Gibbs<R>& G)
+{
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        half_exp_pair<R>(m.b[a], p1[a], m1[a]);  // e^{+-b/2}
-        p2[a] = p1[a] * p1[a];
-        m2[a] = m1[a] * m1[a];                   // e^{+-b}
-        p4[a] = p2[a] * p2[a];
-        m4[a] = m2[a] * m2[a];                   // e^{+-2b}
+        half_exp_pair<R>(m.b[a], G.p1[a], G.m1[a]);  // e^{+-b/2}
+        G.p2[a] = G.p1[a] * G.p1[a];
+        G.m2[a] = G.m1[a] * G.m1[a];                 // e^{+-b}
+        G.p4[a] = G.p2[a] * G.p2[a];
+        G.m4[a] = G.m2[a] * G.m2[a];                 // e^{+-2b}
     }
     const R t = d_exp<R>(R(-0.25) * m.g);
     const R t2 = t * t, t3 = t2 * t, t4 = t2 * t2, t8 = t4 * t4, t12 = t8 * t4, t16 = t8 * t8;
-    const R T[6] = {R(W_REST), R(W_SC1) * t4, R(W_SC2) * t16, R(W_FCC) * t8, R(W_BCC) * t12, R(W_HALF) * t3};
+    G.T[0] = R(W_REST);
+    G.T[1] = R(W_SC1) * t4;
+    G.T[2] = R(W_SC2) * t16;
+    G.T[3] = R(W_FCC) * t8;
+    G.T[4] = R(W_BCC) * t12;
+    G.T[5] = R(W_HALF) * t3;
+    R C[3], D[3], H[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        C[a] = G.p2[a] + G.m2[a];  // 2 cosh b
+        D[a] = G.p4[a] + G.m4[a];  // 2 cosh 2b
+        H[a] = G.p1[a] + G.m1[a];  // 2 cosh b/2
+    }
+    G.Z = G.T[0] + G.T[1] * (C[0] + C[1] + C[2]) + G.T[2] * (D[0] + D[1] + D[2]) +
+          G.T[3] * (C[0] * C[1] + C[0] * C[2] + C[1] * C[2]) + G.T[4] * (C[0] * C[1] * C[2]) +
+          G.T[5] * (H[0] * H[1] * H[2]);
+}
+
+// P_s times the velocity-dependent factor of term q: P_s e^{b.c_q} with
+// P_s standing for (a multiple of) the shell prefactor.
+template <int q, typename R>
+__device__ inline R gibbs_term(const Gibbs<R>& G, const R P[6])
+{
+    constexpr HalfVel v = VEL[q];
     auto fac = [&](int a, int h) -> R {
         switch (h) {
-            case 1: return p1[a];
-            case -1: return m1[a];
-            case 2: return p2[a];
-            case -2: return m2[a];
-            case 4: return p4[a];
-            case -4: return m4[a];
+            case 1: return G.p1[a];
+            case -1: return G.m1[a];
+            case 2: return G.p2[a];
+            case -2: return G.m2[a];
+            case 4: return G.p4[a];
+            case -4: return G.m4[a];
             default: return R(1);
         }
     };
-    R z = R(0);
-    static_for<Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        constexpr HalfVel v = VEL[q];
-        R val = T[v.shell];
-        if constexpr (v.x != 0) val *= fac(0, v.x);
-        if constexpr (v.y != 0) val *= fac(1, v.y);
-        if constexpr (v.z != 0) val *= fac(2, v.z);
-        e[q] = val;
-        z += val;
-    });
-    Z = z;
+    R val = P[v.shell];
+    if constexpr (v.x != 0) val *= fac(0, v.x);
+    if constexpr (v.y != 0) val *= fac(1, v.y);
+    if constexpr (v.z != 0) val *= fac(2, v.z);
+    return val;
 }
+
+// ---------------------------------------------------------------------------
+// Moments of 41 values by shell: for each shell s the plain sum and the sums
+// signed by the sign of c_x, c_y, c_z (the magnitude |c_a| of a shell is
+// applied by the caller). The two 8-velocity shells use a butterfly.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct ShellSums {
+    R s0[6], sx[6], sy[6], sz[6];
+};
+
+template <typename R>
+__device__ inline void cube8(const R* v, R& s0, R& sx, R& sy, R& sz)
+{
+    // order (+++), (++-), (+-+), (+--), (-++), (-+-), (--+), (---)
+    const R a0 = v[0] + v[1], a1 = v[0] - v[1], a2 = v[2] + v[3], a3 = v[2] - v[3];
+    const R a4 = v[4] + v[5], a5 = v[4] - v[5], a6 = v[6] + v[7], a7 = v[6] - v[7];
+    const R b0 = a0 + a2, b1 = a0 - a2, b2 = a1 + a3;
+    const R c0 = a4 + a6, c1 = a4 - a6, c2 = a5 + a7;
+    s0 = b0 + c0;
+    sx = b0 - c0;
+    sy = b1 + c1;
+    sz = b2 + c2;
+}
+
+// four values of one coordinate plane of the fcc shell: (+,+), (+,-), (-,+), (-,-)
+template <typename R>
+__device__ inline void plane4(R pp, R pm, R mp, R mm, R& s0, R& d1, R& d2)
+{
+    const R u1 = pp + pm, u2 = mp + mm, v1 = pp - pm, v2 = mp - mm;
+    s0 = u1 + u2;
+    d1 = u1 - u2;
+    d2 = v1 + v2;
+}
+
+template <typename R>
+__device__ inline void shell_sums(const R x[Q], ShellSums<R>& S)
+{
+    S.s0[0] = x[0];
+    S.sx[0] = S.sy[0] = S.sz[0] = R(0);
+    // sc-1 (q 1..6) and sc-2 (q 7..12): +x, +y, +z, -z, -y, -x
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const R* v = x + 1 + 6 * k;
+        S.s0[1 + k] = (v[0] + v[5]) + (v[1] + v[4]) + (v[2] + v[3]);
+        S.sx[1 + k] = v[0] - v[5];
+        S.sy[1 + k] = v[1] - v[4];
+        S.sz[1 + k] = v[2] - v[3];
+    }
+    // fcc-1 (q 13..24): (1,1,0) (1,0,1) (1,0,-1) (1,-1,0) (0,1,1) (0,1,-1)
+    //                   (0,-1,1) (0,-1,-1) (-1,1,0) (-1,0,1) (-1,0,-1) (-1,-1,0)
+    {
+        const R* v = x + 13;
+        R sxy, dxy_x, dxy_y, sxz, dxz_x, dxz_z, syz, dyz_y, dyz_z;
+        plane4(v[0], v[3], v[8], v[11], sxy, dxy_x, dxy_y);
+        plane4(v[1], v[2], v[9], v[10], sxz, dxz_x, dxz_z);
+        plane4(v[4], v[5], v[6], v[7], syz, dyz_y, dyz_z);
+        S.s0[3] = sxy + sxz + syz;
+        S.sx[3] = dxy_x + dxz_x;
+        S.sy[3] = dxy_y + dyz_y;
+        S.sz[3] = dxz_z + dyz_z;
+    }
+    cube8(x + 25, S.s0[4], S.sx[4], S.sy[4], S.sz[4]);  // bcc-1
+    cube8(x + 33, S.s0[5], S.sx[5], S.sy[5], S.sz[5]);  // bcc-1/2
+}
+
+// |c_a| of a nonzero component and |c|^2, per shell
+constexpr double SHELL_CA[6] = {0.0, 1.0, 2.0, 1.0, 1.0, 0.5};
 
 // ---------------------------------------------------------------------------
 // Storage encodings. Every kernel works on deviations d_q = f_q - w_q rho_ref
@@ -324,38 +418,43 @@ struct StoreF16S {
     __device__ static void store(T* p, R v) { *p = _Float16(v); }  // round to nearest even
 };
 
-// bfloat16 as raw bits: decode by a 16-bit shift, encode with
+// bfloat16 conversions on the host: decode by a 16-bit shift, encode with
 // round-to-nearest-even on the dropped 16 bits (NaN kept quiet).
-__host__ __device__ inline uint16_t f32_to_bf16_rne(float v)
+inline uint16_t host_f32_to_bf16_rne(float v)
 {
-    uint32_t u = __builtin_bit_cast(uint32_t, v);
+    uint32_t u;
+    std::memcpy(&u, &v, 4);
     if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
     u += 0x7fffu + ((u >> 16) & 1u);
     return uint16_t(u >> 16);
 }
-__host__ __device__ inline float bf16_to_f32(uint16_t b)
+inline float host_bf16_to_f32(uint16_t b)
 {
-    return __builtin_bit_cast(float, uint32_t(b) << 16);
+    const uint32_t u = uint32_t(b) << 16;
+    float v;
+    std::memcpy(&v, &u, 4);
+    return v;
 }
 
+// On the device the conversion float -> __bf16 is the hardware
+// round-to-nearest-even conversion of gfx950.
 struct StoreBF16S {
-    using T = uint16_t;
+    using T = __bf16;
     using R = float;
     static constexpr bool shifted = true;
-    __device__ static R load(const T* p) { return bf16_to_f32(*p); }
-    __device__ static void store(T* p, R v) { *p = f32_to_bf16_rne(v); }
+    __device__ static R load(const T* p) { return float(*p); }
+    __device__ static void store(T* p, R v) { *p = __bf16(v); }
 };
 
 // Parameters of the step kernels (passed by value).
 struct StepParams {
     Geom g;
-    double omega;          // relaxation rate (FP64 arithmetic)
-    float omega_f;         // relaxation rate (FP32 arithmetic)
+    double omega;          // relaxation rate
     float scale[6];        // 2^{k_shell + k_amp}   (shifted storage)
     float inv_scale[6];    // 2^{-(k_shell + k_amp)}
-    float wref[6];         // w_shell rho0           (shifted storage; else 0)
-    double rho_ref;        // rho0 (shifted) or 0
-    double e2_ref;         // sum_q w_q rho0 c_q^2 = 3 rho0 theta0 (shifted) or 0
+    float cshift[6];       // -omega w_shell rho0 2^{k_shell + k_amp} (shifted storage)
+    double rho_ref;        // rho0 (shifted) or 0: reference of the stored values
+    double e2_ref;         // sum_q w_q rho_ref c_q^2 = 3 rho_ref theta0
     uint32_t* flag;        // set to 1 when a node has rho <= 0, theta <= 0 or NaN
     uint32_t xcd_remap;    // 1: group consecutive tiles per XCD
 };

@@ -32,44 +32,72 @@ __device__ inline void flag_bad(const StepParams& p, R rho, R theta)
 // periodic), form rho, j, E (Sec. II), solve the entropic equilibrium
 // (Sec. V), relax with the BGK rate omega (Sec. II) and store the
 // post-collision values at the node in the other buffer. One node per
-// thread; every load and store is coalesced along x.
+// thread; every load and store is coalesced along x. Addresses are a
+// per-q scalar base plus a 32-bit byte offset.
+//
+// Moments are formed from deviations from the reference state w_q rho_k:
+// for direct storage d_q = f_q - w_q (exact in floating point while f_q is
+// within a factor two of w_q), for shifted storage the stored h_q scaled
+// per shell. Relaxation f* = (1 - omega) f + omega f_eq is folded into one
+// fused multiply-add per population, with omega rho/Z (and the storage
+// scale) folded into the six shell prefactors of f_eq.
 // ---------------------------------------------------------------------------
 template <class ST, int NEWTON>
 __global__ __launch_bounds__(BLOCK) void k_step(const typename ST::T* __restrict__ fin,
                                                 typename ST::T* __restrict__ fout, StepParams p)
 {
     using R = typename ST::R;
+    using T = typename ST::T;
     const uint32_t blk = p.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     const uint32_t n = blk * BLOCK + threadIdx.x;
     if (n >= p.g.N) return;
     const Coord c = decode(n, p.g);
     Nbr nb;
-    make_nbr(p.g, c, nb);
-    const size_t N = p.g.N;
+    make_nbr(p.g, c, nb, uint32_t(sizeof(T)));
+    const uint64_t qbytes = uint64_t(p.g.N) * sizeof(T);
+    const char* src = reinterpret_cast<const char*>(fin);
+    char* dst = reinterpret_cast<char*>(fout);
 
-    R d[Q];
+    R x[Q];
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        R v = ST::load(fin + size_t(q) * N + pull_src<q>(nb));
-        if constexpr (ST::shifted) v *= p.inv_scale[VEL[q].shell];
-        d[q] = v;
+        x[q] = ST::load(reinterpret_cast<const T*>(src + q * qbytes + uint64_t(pull_src<q>(nb))));
     });
 
-    // moments of the deviations, velocities in half units
-    R rd = R(0), jx = R(0), jy = R(0), jz = R(0), e4 = R(0);
-    static_for<Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        constexpr HalfVel v = VEL[q];
-        rd += d[q];
-        if constexpr (v.x != 0) jx += R(v.x) * d[q];
-        if constexpr (v.y != 0) jy += R(v.y) * d[q];
-        if constexpr (v.z != 0) jz += R(v.z) * d[q];
-        if constexpr (v.shell != 0) e4 += R(v.x * v.x + v.y * v.y + v.z * v.z) * d[q];
-    });
-    const R rho = R(p.rho_ref) + rd;
+    ShellSums<R> S;
+    R rho_k, e2_k;
+    if constexpr (ST::shifted) {
+        shell_sums<R>(x, S);
+        rho_k = R(p.rho_ref);
+        e2_k = R(p.e2_ref);
+    } else {
+        R d[Q];
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            d[q] = x[q] - R(weight(q));
+        });
+        shell_sums<R>(d, S);
+        rho_k = R(1);
+        e2_k = R(3.0 * THETA0);
+    }
+    R drho = R(0), jx = R(0), jy = R(0), jz = R(0), de2 = R(0);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        R k = R(1);
+        if constexpr (ST::shifted) k = R(p.inv_scale[s]);
+        const R s0 = k * S.s0[s];
+        drho += s0;
+        if (s == 0) continue;
+        de2 += R(SHELL_C2[s]) * s0;
+        const R kc = k * R(SHELL_CA[s]);
+        jx += kc * S.sx[s];
+        jy += kc * S.sy[s];
+        jz += kc * S.sz[s];
+    }
+    const R rho = rho_k + drho;
     const R irho = R(1) / rho;
-    const R ux = R(0.5) * jx * irho, uy = R(0.5) * jy * irho, uz = R(0.5) * jz * irho;
-    const R K = (R(p.e2_ref) + R(0.25) * e4) * irho;  // 2E/rho = u^2 + 3 theta
+    const R ux = jx * irho, uy = jy * irho, uz = jz * irho;
+    const R K = (e2_k + de2) * irho;  // 2E/rho = u^2 + 3 theta
     const R u2 = ux * ux + uy * uy + uz * uz;
     const R theta = (K - u2) * R(1.0 / 3.0);
     flag_bad<R>(p, rho, theta);
@@ -83,19 +111,24 @@ __global__ __launch_bounds__(BLOCK) void k_step(const typename ST::T* __restrict
 #pragma unroll
     for (int it = 0; it < NEWTON; ++it) newton_step<R>(m, ux, uy, uz, K);
 
-    R e[Q], Z;
-    gibbs_terms<R>(m, e, Z);
-    const R a = rho / Z;
-    R om;
-    if constexpr (sizeof(R) == 8) om = p.omega; else om = p.omega_f;
+    Gibbs<R> G;
+    gibbs_factors<R>(m, G);
+    const R om = R(p.omega), om1 = R(1) - om;
+    const R oa = om * rho / G.Z;
+    R P[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        P[s] = oa * G.T[s];
+        if constexpr (ST::shifted) P[s] *= R(p.scale[s]);
+    }
+    const uint32_t nbytes = n * uint32_t(sizeof(T));
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        constexpr int sh = VEL[q].shell;
-        R deq = a * e[q];
-        if constexpr (ST::shifted) deq -= p.wref[sh];
-        R v = d[q] + om * (deq - d[q]);
-        if constexpr (ST::shifted) v *= p.scale[sh];
-        ST::store(fout + size_t(q) * N + n, v);
+        const R e = gibbs_term<q, R>(G, P);
+        R v;
+        if constexpr (ST::shifted) v = fma(om1, x[q], e + R(p.cshift[VEL[q].shell]));
+        else v = fma(om1, x[q], e);
+        ST::store(reinterpret_cast<T*>(dst + q * qbytes + uint64_t(nbytes)), v);
     });
 }
 
@@ -116,9 +149,13 @@ __device__ inline void equilibrium_f64(double rho, double ux, double uy, double 
     m.b[2] = uz / theta;
     m.g = 0.5 / theta - 0.5 / THETA0;
     for (int it = 0; it < INIT_NEWTON; ++it) newton_step<double>(m, ux, uy, uz, K);
-    double Z;
-    gibbs_terms<double>(m, e, Z);
-    a = rho / Z;
+    Gibbs<double> G;
+    gibbs_factors<double>(m, G);
+    static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        e[q] = gibbs_term<q, double>(G, G.T);
+    });
+    a = rho / G.Z;
 }
 
 __device__ inline void block_max_float(float v, float* out)

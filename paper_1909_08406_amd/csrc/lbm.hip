@@ -115,6 +115,7 @@ struct lbm_ctx {
     char* staging = nullptr;
     int block_threads = BLOCK;
     int variant = 0;
+    double rho_ref_storage = 0.0;  // rho0 for shifted storage, else 0
 
     char* buf(int i) const { return mem + uint64_t(i) * L.buf_bytes; }
     StepParams params(const BoxDev& b) const
@@ -122,7 +123,8 @@ struct lbm_ctx {
         StepParams p = base;
         p.g = b.g;
         p.omega = b.omega;
-        p.omega_f = float(b.omega);
+        for (int s = 0; s < 6; ++s)
+            p.cshift[s] = float(-b.omega * double(SHELL_W[s]) * rho_ref_storage * double(p.scale[s]));
         return p;
     }
 };
@@ -307,11 +309,11 @@ int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts
     ctx->base.flag = ctx->flag;
     ctx->base.xcd_remap = 1;
     ctx->base.rho_ref = shifted ? ctx->rho0 : 0.0;
+    ctx->rho_ref_storage = ctx->base.rho_ref;
     double e2 = 0.0;  // sum_q w_q c_q^2 rho_ref
     for (int q = 0; q < Q; ++q)
         e2 += SHELL_W[VEL[q].shell] * 0.25 * (VEL[q].x * VEL[q].x + VEL[q].y * VEL[q].y + VEL[q].z * VEL[q].z);
     ctx->base.e2_ref = shifted ? e2 * ctx->rho0 : 0.0;
-    for (int s = 0; s < 6; ++s) ctx->base.wref[s] = shifted ? float(SHELL_W[s] * ctx->rho0) : 0.0f;
     ctx->kamp = 0;
     set_shift(ctx);
 
