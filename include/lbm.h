@@ -189,6 +189,33 @@ int lbm_debug_pull_map(lbm_ctx *ctx, int32_t box, int64_t *src);
 /* Facts about the context (see lbm_info). */
 int lbm_get_info(lbm_ctx *ctx, lbm_info *info);
 
+/* Launch configuration of the step kernel. Every choice computes the same
+ * per-node arithmetic, so results are identical across choices. */
+typedef struct {
+    int32_t variant;    /* 0 .. lbm_num_variants()-1 (block size, cache hints) */
+    int32_t xcd_remap;  /* 1: consecutive tiles on one XCD (L2 domain); 0: dispatch order */
+} lbm_tuning;
+
+/* Number of step-kernel variants. No device needed. */
+int lbm_num_variants(void);
+
+/* Block size and hint flags (1: non-temporal loads, 2: non-temporal stores)
+ * of a variant. No device needed. Errors: LBM_E_ARG. */
+int lbm_variant_desc(int32_t variant, int32_t *block_threads, uint32_t *flags);
+
+/* Select / read the launch configuration of a context. */
+int lbm_set_tuning(lbm_ctx *ctx, const lbm_tuning *t);
+int lbm_get_tuning(lbm_ctx *ctx, lbm_tuning *t);
+
+/*
+ * Time every (variant, xcd_remap) pair with `reps` steps each on the
+ * context's own boxes and keep the fastest. The held state is unchanged
+ * (each timed launch reads the current buffer and writes the other one).
+ * ms (optional) receives 2*lbm_num_variants() mean step times, index
+ * 2*variant + xcd_remap; best (optional) the choice. Synchronous.
+ */
+int lbm_autotune(lbm_ctx *ctx, int32_t reps, float *ms, lbm_tuning *best);
+
 /* The hipStream_t the context queues its work on. */
 void *lbm_stream(lbm_ctx *ctx);
 

@@ -398,6 +398,8 @@ struct StoreF64 {
     using T = double;
     using R = double;
     static constexpr bool shifted = false;
+    __device__ static R decode(T v) { return v; }
+    __device__ static T encode(R v) { return v; }
     __device__ static R load(const T* p) { return *p; }
     __device__ static void store(T* p, R v) { *p = v; }
 };
@@ -406,6 +408,8 @@ struct StoreF32 {
     using T = float;
     using R = float;
     static constexpr bool shifted = false;
+    __device__ static R decode(T v) { return v; }
+    __device__ static T encode(R v) { return v; }
     __device__ static R load(const T* p) { return *p; }
     __device__ static void store(T* p, R v) { *p = v; }
 };
@@ -414,8 +418,10 @@ struct StoreF16S {
     using T = _Float16;
     using R = float;
     static constexpr bool shifted = true;
+    __device__ static R decode(T v) { return float(v); }
+    __device__ static T encode(R v) { return _Float16(v); }  // round to nearest even
     __device__ static R load(const T* p) { return float(*p); }
-    __device__ static void store(T* p, R v) { *p = _Float16(v); }  // round to nearest even
+    __device__ static void store(T* p, R v) { *p = _Float16(v); }
 };
 
 // bfloat16 conversions on the host: decode by a 16-bit shift, encode with
@@ -442,6 +448,8 @@ struct StoreBF16S {
     using T = __bf16;
     using R = float;
     static constexpr bool shifted = true;
+    __device__ static R decode(T v) { return float(v); }
+    __device__ static T encode(R v) { return __bf16(v); }
     __device__ static R load(const T* p) { return float(*p); }
     __device__ static void store(T* p, R v) { *p = __bf16(v); }
 };

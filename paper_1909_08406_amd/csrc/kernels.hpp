@@ -42,14 +42,47 @@ __device__ inline void flag_bad(const StepParams& p, R rho, R theta)
 // fused multiply-add per population, with omega rho/Z (and the storage
 // scale) folded into the six shell prefactors of f_eq.
 // ---------------------------------------------------------------------------
-template <class ST, int NEWTON>
-__global__ __launch_bounds__(BLOCK) void k_step(const typename ST::T* __restrict__ fin,
-                                                typename ST::T* __restrict__ fout, StepParams p)
+// Launch variants (block size, cache-policy hints); the per-node arithmetic
+// is the same in every variant, so results do not depend on the choice.
+constexpr int FL_NT_LOAD = 1;   // non-temporal loads (streamed once)
+constexpr int FL_NT_STORE = 2;  // non-temporal stores
+
+template <class T>
+__device__ inline T ld_hint(const T* p, int nt)
+{
+    if (nt) {
+        if constexpr (sizeof(T) == 2) {
+            const uint16_t b = __builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p));
+            return __builtin_bit_cast(T, b);
+        } else {
+            return __builtin_nontemporal_load(p);
+        }
+    }
+    return *p;
+}
+
+template <class T>
+__device__ inline void st_hint(T* p, T v, int nt)
+{
+    if (nt) {
+        if constexpr (sizeof(T) == 2) {
+            __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), reinterpret_cast<uint16_t*>(p));
+        } else {
+            __builtin_nontemporal_store(v, p);
+        }
+    } else {
+        *p = v;
+    }
+}
+
+template <class ST, int NEWTON, int BLK, int FL>
+__global__ __launch_bounds__(BLK) void k_step(const typename ST::T* __restrict__ fin,
+                                              typename ST::T* __restrict__ fout, StepParams p)
 {
     using R = typename ST::R;
     using T = typename ST::T;
     const uint32_t blk = p.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
-    const uint32_t n = blk * BLOCK + threadIdx.x;
+    const uint32_t n = blk * BLK + threadIdx.x;
     if (n >= p.g.N) return;
     const Coord c = decode(n, p.g);
     Nbr nb;
@@ -61,7 +94,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(const typename ST::T* __restrict
     R x[Q];
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        x[q] = ST::load(reinterpret_cast<const T*>(src + q * qbytes + uint64_t(pull_src<q>(nb))));
+        x[q] = ST::decode(ld_hint(reinterpret_cast<const T*>(src + q * qbytes + uint64_t(pull_src<q>(nb))),
+                                  FL & FL_NT_LOAD));
     });
 
     ShellSums<R> S;
@@ -128,7 +162,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(const typename ST::T* __restrict
         R v;
         if constexpr (ST::shifted) v = fma(om1, x[q], e + R(p.cshift[VEL[q].shell]));
         else v = fma(om1, x[q], e);
-        ST::store(reinterpret_cast<T*>(dst + q * qbytes + uint64_t(nbytes)), v);
+        st_hint(reinterpret_cast<T*>(dst + q * qbytes + uint64_t(nbytes)), ST::encode(v), FL & FL_NT_STORE);
     });
 }
 

@@ -113,7 +113,6 @@ struct lbm_ctx {
     uint32_t* flag = nullptr;
     double* partials = nullptr;
     char* staging = nullptr;
-    int block_threads = BLOCK;
     int variant = 0;
     double rho_ref_storage = 0.0;  // rho0 for shifted storage, else 0
 
@@ -150,28 +149,61 @@ int dispatch_storage(int storage, F&& f)
 
 uint32_t nblocks(uint64_t n) { return uint32_t((n + BLOCK - 1) / BLOCK); }
 
-template <class ST>
-int launch_step_typed(lbm_ctx* ctx, const BoxDev& b, const typename ST::T* in, typename ST::T* out)
+// Step-kernel launch variants: block size and cache-policy hints. The
+// autotuner picks one per context (together with the XCD tile mapping).
+struct VariantDesc {
+    int blk;
+    int fl;
+};
+constexpr VariantDesc VARIANTS[] = {
+    {256, 0}, {256, FL_NT_LOAD | FL_NT_STORE}, {512, 0}, {128, 0}, {256, FL_NT_STORE}, {1024, 0},
+};
+constexpr int NVARIANTS = int(sizeof(VARIANTS) / sizeof(VARIANTS[0]));
+
+template <class ST, int NEWTON, int BLK, int FL>
+void launch_k(const BoxDev& b, hipStream_t st, const typename ST::T* in, typename ST::T* out, const StepParams& p)
 {
-    const StepParams p = ctx->params(b);
-    const dim3 grid(nblocks(b.nodes)), block(BLOCK);
-    switch (ctx->newton) {
-        case 1: hipLaunchKernelGGL((k_step<ST, 1>), grid, block, 0, ctx->stream, in, out, p); break;
-        case 2: hipLaunchKernelGGL((k_step<ST, 2>), grid, block, 0, ctx->stream, in, out, p); break;
-        case 3: hipLaunchKernelGGL((k_step<ST, 3>), grid, block, 0, ctx->stream, in, out, p); break;
-        case 4: hipLaunchKernelGGL((k_step<ST, 4>), grid, block, 0, ctx->stream, in, out, p); break;
+    hipLaunchKernelGGL((k_step<ST, NEWTON, BLK, FL>), dim3(uint32_t((b.nodes + BLK - 1) / BLK)), dim3(BLK), 0, st, in,
+                       out, p);
+}
+
+template <class ST, int NEWTON>
+int launch_variant(int v, const BoxDev& b, hipStream_t st, const typename ST::T* in, typename ST::T* out,
+                   const StepParams& p)
+{
+    switch (v) {
+        case 0: launch_k<ST, NEWTON, 256, 0>(b, st, in, out, p); break;
+        case 1: launch_k<ST, NEWTON, 256, FL_NT_LOAD | FL_NT_STORE>(b, st, in, out, p); break;
+        case 2: launch_k<ST, NEWTON, 512, 0>(b, st, in, out, p); break;
+        case 3: launch_k<ST, NEWTON, 128, 0>(b, st, in, out, p); break;
+        case 4: launch_k<ST, NEWTON, 256, FL_NT_STORE>(b, st, in, out, p); break;
+        case 5: launch_k<ST, NEWTON, 1024, 0>(b, st, in, out, p); break;
         default: return LBM_E_ARG;
     }
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
 }
 
-int launch_step(lbm_ctx* ctx, const BoxDev& b)
+template <class ST>
+int launch_step_typed(lbm_ctx* ctx, const BoxDev& b, const typename ST::T* in, typename ST::T* out)
+{
+    const StepParams p = ctx->params(b);
+    switch (ctx->newton) {
+        case 1: return launch_variant<ST, 1>(ctx->variant, b, ctx->stream, in, out, p);
+        case 2: return launch_variant<ST, 2>(ctx->variant, b, ctx->stream, in, out, p);
+        case 3: return launch_variant<ST, 3>(ctx->variant, b, ctx->stream, in, out, p);
+        case 4: return launch_variant<ST, 4>(ctx->variant, b, ctx->stream, in, out, p);
+        default: return LBM_E_ARG;
+    }
+}
+
+// One step of box b from buffer `from` into the other buffer.
+int launch_step(lbm_ctx* ctx, const BoxDev& b, int from)
 {
     return dispatch_storage(ctx->storage, [&](auto st) {
         using ST = decltype(st);
         using T = typename ST::T;
-        const T* in = reinterpret_cast<const T*>(ctx->buf(ctx->cur)) + b.offset;
-        T* out = reinterpret_cast<T*>(ctx->buf(1 - ctx->cur)) + b.offset;
+        const T* in = reinterpret_cast<const T*>(ctx->buf(from)) + b.offset;
+        T* out = reinterpret_cast<T*>(ctx->buf(1 - from)) + b.offset;
         return launch_step_typed<ST>(ctx, b, in, out);
     });
 }
@@ -361,7 +393,7 @@ int lbm_step(lbm_ctx* ctx, int32_t n)
     if (!ctx || n < 0) return LBM_E_ARG;
     for (int32_t i = 0; i < n; ++i) {
         for (const BoxDev& b : ctx->boxes) {
-            int rc = launch_step(ctx, b);
+            int rc = launch_step(ctx, b, ctx->cur);
             if (rc) return rc;
         }
         ctx->cur ^= 1;
@@ -559,9 +591,87 @@ int lbm_get_info(lbm_ctx* ctx, lbm_info* info)
     info->nboxes = int32_t(ctx->boxes.size());
     info->nodes = int64_t(ctx->L.elems / Q);
     info->bytes_per_step = int64_t(2 * ctx->L.elems * uint64_t(elem_bytes(ctx->storage)));
-    info->block_threads = ctx->block_threads;
+    info->block_threads = VARIANTS[ctx->variant].blk;
     info->variant = ctx->variant;
     info->device_bytes = ctx->L.total;
+    return LBM_OK;
+}
+
+int lbm_num_variants(void) { return NVARIANTS; }
+
+int lbm_variant_desc(int32_t variant, int32_t* block_threads, uint32_t* flags)
+{
+    if (variant < 0 || variant >= NVARIANTS) return LBM_E_ARG;
+    if (block_threads) *block_threads = VARIANTS[variant].blk;
+    if (flags) *flags = uint32_t(VARIANTS[variant].fl);
+    return LBM_OK;
+}
+
+int lbm_set_tuning(lbm_ctx* ctx, const lbm_tuning* t)
+{
+    if (!ctx || !t || t->variant < 0 || t->variant >= NVARIANTS || (t->xcd_remap != 0 && t->xcd_remap != 1))
+        return LBM_E_ARG;
+    ctx->variant = t->variant;
+    ctx->base.xcd_remap = uint32_t(t->xcd_remap);
+    return LBM_OK;
+}
+
+int lbm_get_tuning(lbm_ctx* ctx, lbm_tuning* t)
+{
+    if (!ctx || !t) return LBM_E_ARG;
+    t->variant = ctx->variant;
+    t->xcd_remap = int32_t(ctx->base.xcd_remap);
+    return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx* ctx, int32_t reps, float* ms, lbm_tuning* best)
+{
+    if (!ctx || reps < 1) return LBM_E_ARG;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return LBM_E_HIP;
+    }
+    const int saved_v = ctx->variant;
+    const uint32_t saved_x = ctx->base.xcd_remap;
+    int rc = LBM_OK;
+    float best_ms = 0.f;
+    lbm_tuning bt{saved_v, int32_t(saved_x)};
+    for (int v = 0; v < NVARIANTS && rc == LBM_OK; ++v) {
+        for (int x = 0; x < 2 && rc == LBM_OK; ++x) {
+            ctx->variant = v;
+            ctx->base.xcd_remap = uint32_t(x);
+            // reads the current buffer, writes the other one, never flips:
+            // the held state is left unchanged
+            for (int r = -1; r < reps && rc == LBM_OK; ++r) {
+                if (r == 0 && hipEventRecord(e0, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
+                for (const BoxDev& b : ctx->boxes)
+                    if (rc == LBM_OK) rc = launch_step(ctx, b, ctx->cur);
+            }
+            if (rc == LBM_OK && hipEventRecord(e1, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
+            if (rc == LBM_OK && hipEventSynchronize(e1) != hipSuccess) rc = LBM_E_HIP;
+            float t = 0.f;
+            if (rc == LBM_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = LBM_E_HIP;
+            t /= float(reps);
+            if (ms) ms[2 * v + x] = t;
+            if (rc == LBM_OK && (best_ms == 0.f || t < best_ms)) {
+                best_ms = t;
+                bt.variant = v;
+                bt.xcd_remap = x;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != LBM_OK) {
+        ctx->variant = saved_v;
+        ctx->base.xcd_remap = saved_x;
+        return rc;
+    }
+    ctx->variant = bt.variant;
+    ctx->base.xcd_remap = uint32_t(bt.xcd_remap);
+    if (best) *best = bt;
     return LBM_OK;
 }
 

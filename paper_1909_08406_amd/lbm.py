@@ -45,6 +45,10 @@ class Info(ctypes.Structure):
                 ("block_threads", ctypes.c_int32), ("variant", ctypes.c_int32), ("device_bytes", ctypes.c_uint64)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+
+
 _dp = ctypes.POINTER(ctypes.c_double)
 _lp = ctypes.POINTER(ctypes.c_int64)
 _vp = ctypes.c_void_p
@@ -66,6 +70,12 @@ SIGNATURES = {
     "lbm_gather": (ctypes.c_int, [_vp, ctypes.c_int32, _lp, ctypes.c_int64, _dp]),
     "lbm_debug_pull_map": (ctypes.c_int, [_vp, ctypes.c_int32, _lp]),
     "lbm_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
+    "lbm_num_variants": (ctypes.c_int, []),
+    "lbm_variant_desc": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_uint32)]),
+    "lbm_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
+    "lbm_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
+    "lbm_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(Tuning)]),
     "lbm_stream": (_vp, [_vp]),
     "lbm_free": (None, [_vp]),
     "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -202,6 +212,24 @@ class Context:
     def stream(self):
         return lib().lbm_stream(self.handle)
 
+    def set_tuning(self, variant, xcd_remap):
+        t = Tuning(int(variant), int(xcd_remap))
+        _check(lib().lbm_set_tuning(self.handle, ctypes.byref(t)), "lbm_set_tuning")
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(lib().lbm_get_tuning(self.handle, ctypes.byref(t)), "lbm_get_tuning")
+        return t.variant, t.xcd_remap
+
+    def autotune(self, reps=3):
+        """Times every launch configuration, keeps the fastest; returns
+        ((variant, xcd_remap), {(variant, xcd_remap): ms per step})."""
+        nv = num_variants()
+        ms = (ctypes.c_float * (2 * nv))()
+        best = Tuning()
+        _check(lib().lbm_autotune(self.handle, int(reps), ms, ctypes.byref(best)), "lbm_autotune")
+        return (best.variant, best.xcd_remap), {(v, x): ms[2 * v + x] for v in range(nv) for x in range(2)}
+
     def free(self):
         if self._h is not None:
             lib().lbm_free(self._h)
@@ -245,3 +273,14 @@ def init(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0
 
 def selftest():
     return int(lib().lbm_selftest())
+
+
+def num_variants():
+    return int(lib().lbm_num_variants())
+
+
+def variant_desc(v):
+    b = ctypes.c_int32(0)
+    f = ctypes.c_uint32(0)
+    _check(lib().lbm_variant_desc(int(v), ctypes.byref(b), ctypes.byref(f)), "lbm_variant_desc")
+    return int(b.value), int(f.value)
