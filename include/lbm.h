@@ -65,8 +65,13 @@ typedef enum {
     LBM_F64 = 0,        /* f in FP64                          [FP64] */
     LBM_F32 = 1,        /* f in FP32                          [FP32] */
     LBM_F16_SHIFT = 2,  /* FP16 of (f - w_q rho0) * 2^k_q     [FP32] */
-    LBM_BF16_SHIFT = 3  /* BF16 of (f - w_q rho0) * 2^k_q     [FP32] */
+    LBM_BF16_SHIFT = 3, /* BF16 of (f - w_q rho0) * 2^k_q     [FP32] */
+    LBM_F32_SHIFT = 4   /* FP32 of (f - w_q rho0)              [FP32] */
 } lbm_storage;
+
+/* lbm_opts.flags */
+#define LBM_FLAG_STOCHASTIC_ROUNDING 1u /* round stored values stochastically (unbiased):
+                                           LBM_F32, LBM_F16_SHIFT, LBM_BF16_SHIFT only */
 
 /* Meaning of lbm_box.tau. */
 typedef enum {
@@ -91,8 +96,8 @@ typedef struct {
                              (1 with FP32 arithmetic, 3 with FP64) */
     int32_t shift_exp;    /* k_amp of the shifted storage, k_q = k_shell(q) + k_amp;
                              LBM_SHIFT_AUTO picks it from the initial state */
-    uint32_t flags;       /* 0; reserved */
-    int32_t reserved;     /* must be 0 */
+    uint32_t flags;       /* LBM_FLAG_* */
+    uint32_t seed;        /* seed of the stochastic rounding */
 } lbm_opts;
 
 /* Read-only facts about a context. */
@@ -106,6 +111,8 @@ typedef struct {
     int32_t block_threads;      /* launch configuration of the step kernel */
     int32_t variant;            /* step-kernel variant id */
     uint64_t device_bytes;      /* device memory held by the context */
+    uint32_t flags;             /* LBM_FLAG_* in effect */
+    uint32_t steps_done;        /* step counter (seeds the stochastic rounding) */
 } lbm_info;
 
 typedef struct lbm_ctx lbm_ctx; /* opaque, owned by the library */
@@ -160,6 +167,16 @@ int lbm_moments(lbm_ctx *ctx, double *rho, double *jx, double *jy, double *jz, d
  */
 int lbm_totals(lbm_ctx *ctx, double *out);
 
+/*
+ * Fourier amplitudes of the node fields of one box at wavevector k[3]
+ * (radians per cell spacing): out[2f] + i out[2f+1] = (1/N) sum_n m_f(n)
+ * exp(-i k.x_n) for m_f = rho, jx, jy, jz, E, theta (f = 0..5), with x_n the
+ * node position (sublattice 1 offset by half a cell in every direction) and
+ * theta = (2E/rho - u^2)/3 (Sec. II). Summed in FP64 on the device, without
+ * copying fields to the host. Synchronous. Errors: LBM_E_ARG.
+ */
+int lbm_project(lbm_ctx *ctx, int32_t box, const double *k, double *out);
+
 /* LBM_OK, or LBM_E_NONFINITE once a step has flagged a node. Synchronous. */
 int lbm_status(lbm_ctx *ctx);
 
@@ -185,6 +202,10 @@ int lbm_gather(lbm_ctx *ctx, int32_t box, const int64_t *idx, int64_t count, dou
  * the node whose population q the step pulls into node n. Synchronous.
  */
 int lbm_debug_pull_map(lbm_ctx *ctx, int32_t box, int64_t *src);
+
+/* Set the step counter that seeds the stochastic rounding (restore it with
+ * the populations to resume a run bit for bit). */
+int lbm_set_step_counter(lbm_ctx *ctx, uint32_t steps_done);
 
 /* Facts about the context (see lbm_info). */
 int lbm_get_info(lbm_ctx *ctx, lbm_info *info);
@@ -231,6 +252,15 @@ const char *lbm_strerror(int code);
  * No device needed.
  */
 int lbm_selftest(void);
+
+/*
+ * The step kernel's per-node collision (Sec. II with the equilibrium of
+ * Sec. V), run on the host with the same arithmetic in FP64 (precision 0)
+ * or FP32 (precision 1) and `newton` Newton steps: f_out = C[f_in] for one
+ * node's 41 populations (direct storage; inputs rounded to the precision).
+ * For testing the arithmetic without a device. Errors: LBM_E_ARG.
+ */
+int lbm_collide_host(int32_t precision, int32_t newton, double omega, const double *f_in, double *f_out);
 
 #ifdef __cplusplus
 }

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cmath>
 #include <cstring>
 
 #include "lattice.hpp"
@@ -139,35 +140,51 @@ __device__ inline uint32_t pull_src(const Nbr& nb)
 // ---------------------------------------------------------------------------
 // Arithmetic helpers per compute type.
 // ---------------------------------------------------------------------------
-template <typename R> __device__ inline R d_exp(R x);
-template <> __device__ inline float d_exp<float>(float x) { return __expf(x); }
-template <> __device__ inline double d_exp<double>(double x) { return exp(x); }
-
-template <typename R> __device__ inline R d_rcp(R x);
-template <> __device__ inline float d_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ inline double d_rcp<double>(double x) { return 1.0 / x; }
-
-// e^{h/2} and e^{-h/2}
-template <typename R>
-__device__ inline void half_exp_pair(R h, R& ep, R& em)
+// The equilibrium and collision code below is __host__ __device__ so that
+// the library can run the very same arithmetic on the host for testing;
+// only these two helpers differ (hardware exp/reciprocal on the device).
+template <typename R> __host__ __device__ inline R d_exp(R x);
+template <> __host__ __device__ inline float d_exp<float>(float x)
 {
-    ep = d_exp<R>(R(0.5) * h);
-    if constexpr (sizeof(R) == 4) em = d_exp<R>(R(-0.5) * h);
-    else em = d_rcp<R>(ep);
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __expf(x);
+#else
+    return std::exp(x);
+#endif
 }
+template <> __host__ __device__ inline double d_exp<double>(double x) { return exp(x); }
+
+template <typename R> __host__ __device__ inline R d_rcp(R x);
+template <> __host__ __device__ inline float d_rcp<float>(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+template <> __host__ __device__ inline double d_rcp<double>(double x) { return 1.0 / x; }
 
 // ---------------------------------------------------------------------------
-// Exact entropic equilibrium (Sec. V).
+// Exact entropic equilibrium (Sec. V), in deviation form.
 //
 // With f_eq,i = rho w_i e^{b.c_i - g c_i^2} / Z(b, g) and
 // Z = sum_i w_i e^{b.c_i - g c_i^2} (the paper's beta = -b, gamma = g,
 // alpha = ln Z), mass holds by construction and momentum and energy require
-//     d lnZ / d b = u,   -d lnZ / d g = u^2 + 3 theta = K.
-// Z sums in closed form over the six shells with cosh/sinh of b_a/2, b_a,
-// 2 b_a and powers of t = e^{-g/4}. Newton minimises the convex function
-// lnZ - b.u + g K; its Hessian is the 4x4 covariance of (c, -c^2) under
-// the equilibrium, symmetric positive definite. Start: the continuous
-// Maxwellian, b = u/theta, g = 1/(2 theta) - 1/(2 theta0).
+//     d lnZ / d b = u,   -d lnZ / d g = u^2 + 3 theta.
+// Z sums in closed form over the six shells (cosh/sinh of b_a/2, b_a, 2 b_a
+// and powers of t = e^{-g/4}). Newton minimises the convex function
+// lnZ - b.u + g (u^2 + 3 theta), whose Hessian is the 4x4 covariance of
+// (c, -c^2) under the equilibrium. Start: the continuous Maxwellian,
+// b = u/theta, g = 1/(2 theta) - 1/(2 theta0).
+//
+// Everything that decides conservation is carried as a deviation from the
+// reference state w_i rho_ref (whose multipliers are zero): e^{b.c - g c^2}
+// - 1 is formed from sinh and cosh - 1 of the multipliers and expm1 of the
+// temperature multiplier, never as a difference of two numbers near one.
+// The normalisation enters as kappa with rho/Z = rho_ref (1 + kappa), so a
+// collision conserves mass, momentum and energy to the rounding of small
+// quantities, whatever the rounding of the weights themselves.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct Mult {
@@ -175,63 +192,204 @@ struct Mult {
     R g;
 };
 
+// sinh(x) and cosh(x) - 1, accurate for small |x| (Taylor series to the
+// precision of R for |x| <= 1, exponentials beyond).
 template <typename R>
-__device__ inline void newton_step(Mult<R>& m, R ux, R uy, R uz, R K)
+__host__ __device__ inline void hyp(R x, R& sh, R& chm)
 {
-    const R w0 = R(W_REST), w1 = R(W_SC1), w2 = R(W_SC2), w3 = R(W_FCC), w4 = R(W_BCC), w5 = R(W_HALF);
-    R Ch[3], Sh[3], C1[3], S1[3], C2[3], S2[3];
+    const R x2 = x * x;
+    if constexpr (sizeof(R) == 4) {
+        sh = x * (R(1) + x2 * (R(1.0 / 6) + x2 * (R(1.0 / 120) + x2 * (R(1.0 / 5040) + x2 * (R(1.0 / 362880) +
+                  x2 * R(1.0 / 39916800))))));
+        chm = x2 * (R(0.5) + x2 * (R(1.0 / 24) + x2 * (R(1.0 / 720) + x2 * (R(1.0 / 40320) + x2 * (R(1.0 / 3628800) +
+                    x2 * R(1.0 / 479001600))))));
+    } else {
+        R ps = R(1.0 / 121645100408832000.0);  // 1/19!
+        R pc = R(1.0 / 2432902008176640000.0); // 1/20!
+        ps = R(1.0 / 355687428096000.0) + x2 * ps;      // 1/17!
+        pc = R(1.0 / 6402373705728000.0) + x2 * pc;     // 1/18!
+        ps = R(1.0 / 1307674368000.0) + x2 * ps;        // 1/15!
+        pc = R(1.0 / 20922789888000.0) + x2 * pc;       // 1/16!
+        ps = R(1.0 / 6227020800.0) + x2 * ps;           // 1/13!
+        pc = R(1.0 / 87178291200.0) + x2 * pc;          // 1/14!
+        ps = R(1.0 / 39916800.0) + x2 * ps;             // 1/11!
+        pc = R(1.0 / 479001600.0) + x2 * pc;            // 1/12!
+        ps = R(1.0 / 362880.0) + x2 * ps;               // 1/9!
+        pc = R(1.0 / 3628800.0) + x2 * pc;              // 1/10!
+        ps = R(1.0 / 5040.0) + x2 * ps;                 // 1/7!
+        pc = R(1.0 / 40320.0) + x2 * pc;                // 1/8!
+        ps = R(1.0 / 120.0) + x2 * ps;                  // 1/5!
+        pc = R(1.0 / 720.0) + x2 * pc;                  // 1/6!
+        ps = R(1.0 / 6.0) + x2 * ps;                    // 1/3!
+        pc = R(1.0 / 24.0) + x2 * pc;                   // 1/4!
+        sh = x * (R(1) + x2 * ps);
+        chm = x2 * (R(0.5) + x2 * pc);
+    }
+    if (__builtin_expect(x2 > R(1), 0)) {
+        const R ep = d_exp<R>(x), em = d_exp<R>(-x);
+        sh = R(0.5) * (ep - em);
+        chm = R(0.5) * (ep + em) - R(1);
+    }
+}
+
+// e^y - 1, accurate for small |y| (series for |y| <= 1/2, exponential beyond).
+template <typename R>
+__host__ __device__ inline R expm1_dev(R y)
+{
+    R p;
+    if constexpr (sizeof(R) == 4) {
+        p = R(1.0 / 362880);
+        p = R(1.0 / 40320) + y * p;
+        p = R(1.0 / 5040) + y * p;
+        p = R(1.0 / 720) + y * p;
+        p = R(1.0 / 120) + y * p;
+        p = R(1.0 / 24) + y * p;
+        p = R(1.0 / 6) + y * p;
+        p = R(0.5) + y * p;
+    } else {
+        p = R(1.0 / 6402373705728000.0);  // 1/18!
+        const double inv_fact[] = {1.0 / 355687428096000.0, 1.0 / 20922789888000.0, 1.0 / 1307674368000.0,
+                                   1.0 / 87178291200.0, 1.0 / 6227020800.0, 1.0 / 479001600.0, 1.0 / 39916800.0,
+                                   1.0 / 3628800.0, 1.0 / 362880.0, 1.0 / 40320.0, 1.0 / 5040.0, 1.0 / 720.0,
+                                   1.0 / 120.0, 1.0 / 24.0, 1.0 / 6.0, 0.5};
+#pragma unroll
+        for (int i = 0; i < 16; ++i) p = R(inv_fact[i]) + y * p;
+    }
+    R r = y + y * y * p;
+    if (__builtin_expect(y * y > R(0.25), 0)) r = d_exp<R>(y) - R(1);
+    return r;
+}
+
+// (1 + a)(1 + b) - 1
+template <typename R>
+__host__ __device__ inline R dmul(R a, R b)
+{
+    return fma(a, b, a + b);
+}
+
+// Shell structure of the Gibbs factors at multipliers (b, g).
+template <typename R>
+struct Shells {
+    // per axis: sinh and cosh-1 of b/2, b and 2b
+    R sh[3], chm[3], s1[3], c1m[3], s2[3], c2m[3];
+    // t^k - 1 for t = e^{-g/4}, the shell exponents k = 4|c|^2: 3, 4, 8, 12, 16
+    R tau[6];  // indexed by shell (tau[0] = 0 for the rest velocity)
+    R zdev[6]; // shell contributions to Z - sum_i w_i
+    R zeta;    // Z - sum_i w_i
+    R Z;
+};
+
+// |c|^2 of each shell as stored with R: 0, 1, 4, 2, 3, 3/4.
+template <typename R>
+__host__ __device__ inline void shells_at(const Mult<R>& m, Shells<R>& S)
+{
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        R ep, em;
-        half_exp_pair<R>(m.b[a], ep, em);
-        Ch[a] = R(0.5) * (ep + em);
-        Sh[a] = R(0.5) * (ep - em);
-        C1[a] = R(1) + R(2) * Sh[a] * Sh[a];
-        S1[a] = R(2) * Sh[a] * Ch[a];
-        C2[a] = R(1) + R(2) * S1[a] * S1[a];
-        S2[a] = R(2) * S1[a] * C1[a];
+        hyp<R>(R(0.5) * m.b[a], S.sh[a], S.chm[a]);
+        S.s1[a] = R(2) * S.sh[a] * (R(1) + S.chm[a]);  // sinh b
+        S.c1m[a] = R(2) * S.sh[a] * S.sh[a];           // cosh b - 1
+        S.s2[a] = R(2) * S.s1[a] * (R(1) + S.c1m[a]);  // sinh 2b
+        S.c2m[a] = R(2) * S.s1[a] * S.s1[a];           // cosh 2b - 1
     }
-    const R t = d_exp<R>(R(-0.25) * m.g);
-    const R t2 = t * t, t3 = t2 * t, t4 = t2 * t2, t8 = t4 * t4, t12 = t8 * t4, t16 = t8 * t8;
-    const R T1 = w1 * t4, T2 = w2 * t16, T3 = w3 * t8, T4 = w4 * t12, T5 = w5 * t3;
+    const R t1 = expm1_dev<R>(R(-0.25) * m.g);
+    const R t2 = dmul(t1, t1), t3 = dmul(t2, t1), t4 = dmul(t2, t2), t8 = dmul(t4, t4), t12 = dmul(t8, t4),
+            t16 = dmul(t8, t8);
+    S.tau[0] = R(0);
+    S.tau[1] = t4;
+    S.tau[2] = t16;
+    S.tau[3] = t8;
+    S.tau[4] = t12;
+    S.tau[5] = t3;
+    // shell sums of the axis factors, as deviations from their value at b = 0
+    const R sc1 = S.c1m[0] + S.c1m[1] + S.c1m[2];                         // sum (cosh b - 1)
+    const R sc2 = S.c2m[0] + S.c2m[1] + S.c2m[2];                         // sum (cosh 2b - 1)
+    const R pxy = dmul(S.c1m[0], S.c1m[1]), pxz = dmul(S.c1m[0], S.c1m[2]), pyz = dmul(S.c1m[1], S.c1m[2]);
+    const R p3 = dmul(pxy, S.c1m[2]);                                     // prod cosh b - 1
+    const R h3 = dmul(dmul(S.chm[0], S.chm[1]), S.chm[2]);                // prod cosh b/2 - 1
+    S.zdev[0] = R(0);
+    S.zdev[1] = R(2 * W_SC1) * (R(3) * t4 + (R(1) + t4) * sc1);
+    S.zdev[2] = R(2 * W_SC2) * (R(3) * t16 + (R(1) + t16) * sc2);
+    S.zdev[3] = R(4 * W_FCC) * (R(3) * t8 + (R(1) + t8) * (pxy + pxz + pyz));
+    S.zdev[4] = R(8 * W_BCC) * dmul(t12, p3);
+    S.zdev[5] = R(8 * W_HALF) * dmul(t3, h3);
+    S.zeta = S.zdev[1] + S.zdev[2] + S.zdev[3] + S.zdev[4] + S.zdev[5];
+    S.Z = R(SUM_W) + S.zeta;
+}
 
-    // pair products of the fcc shell and triple products of the bcc shells
-    const R Pxy = C1[0] * C1[1], Pxz = C1[0] * C1[2], Pyz = C1[1] * C1[2];
-    const R P3 = Pxy * C1[2];
-    const R H3 = Ch[0] * Ch[1] * Ch[2];
+// Node state entering the equilibrium: deviations of the conserved sums
+// from the reference state w_i rho_ref, and rho itself.
+template <typename R>
+struct NodeDev {
+    R rho, irho;     // density and 1/rho
+    R drho;          // sum_i f_i - rho_ref sum_i w_i
+    R j[3];          // momentum sum_i f_i c_i
+    R de2;           // sum_i f_i c_i^2 - rho_ref sum_i w_i c_i^2
+    R rho_ref;
+};
+
+// kappa with rho/Z = rho_ref (1 + kappa)
+template <typename R>
+__host__ __device__ inline R kappa_of(const NodeDev<R>& st, const Shells<R>& S)
+{
+    return (st.drho - st.rho_ref * S.zeta) / (st.rho_ref * S.Z);
+}
+
+template <typename R>
+__host__ __device__ inline void newton_step(Mult<R>& m, const NodeDev<R>& st)
+{
+    Shells<R> S;
+    shells_at<R>(m, S);
+    const R T1 = R(W_SC1) * (R(1) + S.tau[1]), T2 = R(W_SC2) * (R(1) + S.tau[2]),
+            T3 = R(W_FCC) * (R(1) + S.tau[3]), T4 = R(W_BCC) * (R(1) + S.tau[4]),
+            T5 = R(W_HALF) * (R(1) + S.tau[5]);
+    R C1[3], Ch[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        C1[a] = R(1) + S.c1m[a];
+        Ch[a] = R(1) + S.chm[a];
+    }
+    const R Z = S.Z, iz = R(1) / Z;
+    // <c^2> Z = sum_s |c_s|^2 (shell part of Z); its deviation is eta2
+    const R eta2 = S.zdev[1] + R(4) * S.zdev[2] + R(2) * S.zdev[3] + R(3) * S.zdev[4] + R(0.75) * S.zdev[5];
+    const R N2 = R(SUM_WC2) + eta2;
+    // Z-weighted moments for the Hessian
     const R sc1 = R(2) * T1 * (C1[0] + C1[1] + C1[2]);
-    const R sc2 = R(2) * T2 * (C2[0] + C2[1] + C2[2]);
-    const R fcc = R(4) * T3 * (Pxy + Pxz + Pyz);
-    const R bcc = R(8) * T4 * P3;
-    const R hlf = R(8) * T5 * H3;
-
-    const R Z = w0 + sc1 + sc2 + fcc + bcc + hlf;                               // <1>
-    const R N2 = sc1 + R(4) * sc2 + R(2) * fcc + R(3) * bcc + R(0.75) * hlf;     // <c^2>
-    const R N4 = sc1 + R(16) * sc2 + R(4) * fcc + R(9) * bcc + R(0.5625) * hlf;  // <c^4>
-
+    const R sc2 = R(2) * T2 * (R(3) + S.c2m[0] + S.c2m[1] + S.c2m[2]);
+    const R fcc = R(4) * T3 * (C1[0] * C1[1] + C1[0] * C1[2] + C1[1] * C1[2]);
+    const R bcc = R(8) * T4 * (C1[0] * C1[1] * C1[2]);
+    const R hlf = R(8) * T5 * (Ch[0] * Ch[1] * Ch[2]);
+    const R N4 = sc1 + R(16) * sc2 + R(4) * fcc + R(9) * bcc + R(0.5625) * hlf;
     R M[3], XX[3], XC[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int b = (a + 1) % 3, c = (a + 2) % 3;
-        const R s1 = R(2) * T1 * S1[a];
-        const R s2 = R(4) * T2 * S2[a];
-        const R f = R(4) * T3 * S1[a] * (C1[b] + C1[c]);
-        const R bb = R(8) * T4 * S1[a] * C1[b] * C1[c];
-        const R hh = R(4) * T5 * Sh[a] * Ch[b] * Ch[c];
-        M[a] = s1 + s2 + f + bb + hh;                                          // <c_a>
-        XC[a] = s1 + R(4) * s2 + R(2) * f + R(3) * bb + R(0.75) * hh;          // <c_a c^2>
-        XX[a] = R(2) * T1 * C1[a] + R(8) * T2 * C2[a] + R(4) * T3 * C1[a] * (C1[b] + C1[c]) + bcc + R(0.25) * hlf;  // <c_a^2>
+        const R s1 = R(2) * T1 * S.s1[a];
+        const R s2 = R(4) * T2 * S.s2[a];
+        const R f = R(4) * T3 * S.s1[a] * (C1[b] + C1[c]);
+        const R bb = R(8) * T4 * S.s1[a] * C1[b] * C1[c];
+        const R hh = R(4) * T5 * S.sh[a] * Ch[b] * Ch[c];
+        M[a] = s1 + s2 + f + bb + hh;                                   // Z <c_a>
+        XC[a] = s1 + R(4) * s2 + R(2) * f + R(3) * bb + R(0.75) * hh;   // Z <c_a c^2>
+        XX[a] = R(2) * T1 * C1[a] + R(8) * T2 * (R(1) + S.c2m[a]) + R(4) * T3 * C1[a] * (C1[b] + C1[c]) + bcc +
+                R(0.25) * hlf;                                          // Z <c_a^2>
     }
-    // <c_a c_b>, a < b
-    const R XYxy = R(4) * T3 * S1[0] * S1[1] + R(8) * T4 * S1[0] * S1[1] * C1[2] + R(2) * T5 * Sh[0] * Sh[1] * Ch[2];
-    const R XYxz = R(4) * T3 * S1[0] * S1[2] + R(8) * T4 * S1[0] * S1[2] * C1[1] + R(2) * T5 * Sh[0] * Sh[2] * Ch[1];
-    const R XYyz = R(4) * T3 * S1[1] * S1[2] + R(8) * T4 * S1[1] * S1[2] * C1[0] + R(2) * T5 * Sh[1] * Sh[2] * Ch[0];
+    const R XYxy = R(4) * T3 * S.s1[0] * S.s1[1] + R(8) * T4 * S.s1[0] * S.s1[1] * C1[2] +
+                   R(2) * T5 * S.sh[0] * S.sh[1] * Ch[2];
+    const R XYxz = R(4) * T3 * S.s1[0] * S.s1[2] + R(8) * T4 * S.s1[0] * S.s1[2] * C1[1] +
+                   R(2) * T5 * S.sh[0] * S.sh[2] * Ch[1];
+    const R XYyz = R(4) * T3 * S.s1[1] * S.s1[2] + R(8) * T4 * S.s1[1] * S.s1[2] * C1[0] +
+                   R(2) * T5 * S.sh[1] * S.sh[2] * Ch[0];
 
-    const R iz = d_rcp<R>(Z);
+    // gradient of lnZ - b.u + g (u^2 + 3 theta), formed from deviations:
+    //   rho (<c> - u)             = rho_ref (1 + kappa) Z<c> - j
+    //   rho (u^2 + 3 theta - <c^2>) = de2 - rho_ref (eta2 + kappa (sum w c^2 + eta2))
+    const R kap = kappa_of<R>(st, S);
+    const R r0 = (st.rho_ref * (R(1) + kap) * M[0] - st.j[0]) * st.irho;
+    const R r1 = (st.rho_ref * (R(1) + kap) * M[1] - st.j[1]) * st.irho;
+    const R r2 = (st.rho_ref * (R(1) + kap) * M[2] - st.j[2]) * st.irho;
+    const R r3 = (st.de2 - st.rho_ref * (eta2 + kap * N2)) * st.irho;
+
     const R mu0 = M[0] * iz, mu1 = M[1] * iz, mu2 = M[2] * iz, m2 = N2 * iz;
-    // gradient of lnZ - b.u + g K
-    const R r0 = mu0 - ux, r1 = mu1 - uy, r2 = mu2 - uz, r3 = K - m2;
-    // Hessian (covariance of (c, -c^2))
     const R H00 = XX[0] * iz - mu0 * mu0, H11 = XX[1] * iz - mu1 * mu1, H22 = XX[2] * iz - mu2 * mu2;
     const R H10 = XYxy * iz - mu1 * mu0, H20 = XYxz * iz - mu2 * mu0, H21 = XYyz * iz - mu2 * mu1;
     const R H30 = m2 * mu0 - XC[0] * iz, H31 = m2 * mu1 - XC[1] * iz, H32 = m2 * mu2 - XC[2] * iz;
@@ -256,69 +414,27 @@ __device__ inline void newton_step(Mult<R>& m, R ux, R uy, R uz, R K)
     m.g -= x3;
 }
 
-// Factors of the Gibbs terms w_q e^{b.c_q - g c_q^2}: per-axis powers
-// e^{+-b/2}, e^{+-b}, e^{+-2b}, the shell prefactors w_s t^{4 |c_s|^2}
-// (t = e^{-g/4}) and Z = sum_q w_q e^{...} in closed form over the shells.
-template <typename R>
-struct Gibbs {
-    R p1[3], m1[3], p2[3], m2[3], p4[3], m4[3];
-    R T[6];
-    R Z;
-};
-
-template <typename R>
-__device__ inline void gibbs_factors(const Mult<R>& m, Gibbs<R>& G)
-{
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        half_exp_pair<R>(m.b[a], G.p1[a], G.m1[a]);  // e^{+-b/2}
-        G.p2[a] = G.p1[a] * G.p1[a];
-        G.m2[a] = G.m1[a] * G.m1[a];                 // e^{+-b}
-        G.p4[a] = G.p2[a] * G.p2[a];
-        G.m4[a] = G.m2[a] * G.m2[a];                 // e^{+-2b}
-    }
-    const R t = d_exp<R>(R(-0.25) * m.g);
-    const R t2 = t * t, t3 = t2 * t, t4 = t2 * t2, t8 = t4 * t4, t12 = t8 * t4, t16 = t8 * t8;
-    G.T[0] = R(W_REST);
-    G.T[1] = R(W_SC1) * t4;
-    G.T[2] = R(W_SC2) * t16;
-    G.T[3] = R(W_FCC) * t8;
-    G.T[4] = R(W_BCC) * t12;
-    G.T[5] = R(W_HALF) * t3;
-    R C[3], D[3], H[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        C[a] = G.p2[a] + G.m2[a];  // 2 cosh b
-        D[a] = G.p4[a] + G.m4[a];  // 2 cosh 2b
-        H[a] = G.p1[a] + G.m1[a];  // 2 cosh b/2
-    }
-    G.Z = G.T[0] + G.T[1] * (C[0] + C[1] + C[2]) + G.T[2] * (D[0] + D[1] + D[2]) +
-          G.T[3] * (C[0] * C[1] + C[0] * C[2] + C[1] * C[2]) + G.T[4] * (C[0] * C[1] * C[2]) +
-          G.T[5] * (H[0] * H[1] * H[2]);
-}
-
-// P_s times the velocity-dependent factor of term q: P_s e^{b.c_q} with
-// P_s standing for (a multiple of) the shell prefactor.
+// e^{b.c_q - g c_q^2} - 1 for velocity q, from the shell structure.
 template <int q, typename R>
-__device__ inline R gibbs_term(const Gibbs<R>& G, const R P[6])
+__host__ __device__ inline R gibbs_dev(const Shells<R>& S)
 {
     constexpr HalfVel v = VEL[q];
     auto fac = [&](int a, int h) -> R {
         switch (h) {
-            case 1: return G.p1[a];
-            case -1: return G.m1[a];
-            case 2: return G.p2[a];
-            case -2: return G.m2[a];
-            case 4: return G.p4[a];
-            case -4: return G.m4[a];
-            default: return R(1);
+            case 1: return S.chm[a] + S.sh[a];
+            case -1: return S.chm[a] - S.sh[a];
+            case 2: return S.c1m[a] + S.s1[a];
+            case -2: return S.c1m[a] - S.s1[a];
+            case 4: return S.c2m[a] + S.s2[a];
+            case -4: return S.c2m[a] - S.s2[a];
+            default: return R(0);
         }
     };
-    R val = P[v.shell];
-    if constexpr (v.x != 0) val *= fac(0, v.x);
-    if constexpr (v.y != 0) val *= fac(1, v.y);
-    if constexpr (v.z != 0) val *= fac(2, v.z);
-    return val;
+    R e = S.tau[v.shell];
+    if constexpr (v.x != 0) e = dmul(e, fac(0, v.x));
+    if constexpr (v.y != 0) e = dmul(e, fac(1, v.y));
+    if constexpr (v.z != 0) e = dmul(e, fac(2, v.z));
+    return e;
 }
 
 // ---------------------------------------------------------------------------
@@ -332,7 +448,7 @@ struct ShellSums {
 };
 
 template <typename R>
-__device__ inline void cube8(const R* v, R& s0, R& sx, R& sy, R& sz)
+__host__ __device__ inline void cube8(const R* v, R& s0, R& sx, R& sy, R& sz)
 {
     // order (+++), (++-), (+-+), (+--), (-++), (-+-), (--+), (---)
     const R a0 = v[0] + v[1], a1 = v[0] - v[1], a2 = v[2] + v[3], a3 = v[2] - v[3];
@@ -347,7 +463,7 @@ __device__ inline void cube8(const R* v, R& s0, R& sx, R& sy, R& sz)
 
 // four values of one coordinate plane of the fcc shell: (+,+), (+,-), (-,+), (-,-)
 template <typename R>
-__device__ inline void plane4(R pp, R pm, R mp, R mm, R& s0, R& d1, R& d2)
+__host__ __device__ inline void plane4(R pp, R pm, R mp, R mm, R& s0, R& d1, R& d2)
 {
     const R u1 = pp + pm, u2 = mp + mm, v1 = pp - pm, v2 = mp - mm;
     s0 = u1 + u2;
@@ -356,7 +472,7 @@ __device__ inline void plane4(R pp, R pm, R mp, R mm, R& s0, R& d1, R& d2)
 }
 
 template <typename R>
-__device__ inline void shell_sums(const R x[Q], ShellSums<R>& S)
+__host__ __device__ inline void shell_sums(const R x[Q], ShellSums<R>& S)
 {
     S.s0[0] = x[0];
     S.sx[0] = S.sy[0] = S.sz[0] = R(0);
@@ -398,6 +514,7 @@ struct StoreF64 {
     using T = double;
     using R = double;
     static constexpr bool shifted = false;
+    static constexpr bool unit_scale = true;
     __device__ static R decode(T v) { return v; }
     __device__ static T encode(R v) { return v; }
     __device__ static R load(const T* p) { return *p; }
@@ -408,18 +525,44 @@ struct StoreF32 {
     using T = float;
     using R = float;
     static constexpr bool shifted = false;
+    static constexpr bool unit_scale = true;
     __device__ static R decode(T v) { return v; }
     __device__ static T encode(R v) { return v; }
     __device__ static R load(const T* p) { return *p; }
     __device__ static void store(T* p, R v) { *p = v; }
 };
 
+// FP32 holding the shift h = f - w rho0 (scale 1).
+struct StoreF32S {
+    using T = float;
+    using R = float;
+    static constexpr bool shifted = true;
+    static constexpr bool unit_scale = true;
+    __device__ static R decode(T v) { return v; }
+    __device__ static T encode(R v) { return v; }
+    __device__ static R load(const T* p) { return *p; }
+    __device__ static void store(T* p, R v) { *p = v; }
+};
+
+// Stochastic rounding to a format with `drop` fewer mantissa bits than FP32:
+// add `drop` uniformly random bits below the kept mantissa, then truncate.
+// The result is representable, so the final conversion is exact, and its
+// expectation equals v (away from the format's subnormal range).
+__device__ inline float sr_truncate(float v, uint32_t rbits, int drop)
+{
+    const uint32_t mask = (1u << drop) - 1u;
+    uint32_t u = __float_as_uint(v) + (rbits & mask);
+    return __uint_as_float(u & ~mask);
+}
+
 struct StoreF16S {
     using T = _Float16;
     using R = float;
     static constexpr bool shifted = true;
+    static constexpr bool unit_scale = false;
     __device__ static R decode(T v) { return float(v); }
     __device__ static T encode(R v) { return _Float16(v); }  // round to nearest even
+    __device__ static T encode_sr(R v, uint32_t r) { return _Float16(sr_truncate(v, r, 13)); }
     __device__ static R load(const T* p) { return float(*p); }
     __device__ static void store(T* p, R v) { *p = _Float16(v); }
 };
@@ -448,8 +591,10 @@ struct StoreBF16S {
     using T = __bf16;
     using R = float;
     static constexpr bool shifted = true;
+    static constexpr bool unit_scale = false;
     __device__ static R decode(T v) { return float(v); }
     __device__ static T encode(R v) { return __bf16(v); }
+    __device__ static T encode_sr(R v, uint32_t r) { return __bf16(sr_truncate(v, r, 16)); }
     __device__ static R load(const T* p) { return float(*p); }
     __device__ static void store(T* p, R v) { *p = __bf16(v); }
 };
@@ -460,11 +605,47 @@ struct StepParams {
     double omega;          // relaxation rate
     float scale[6];        // 2^{k_shell + k_amp}   (shifted storage)
     float inv_scale[6];    // 2^{-(k_shell + k_amp)}
-    float cshift[6];       // -omega w_shell rho0 2^{k_shell + k_amp} (shifted storage)
+    float omw[6];          // omega w_shell rho0 2^{k_shell + k_amp} (shifted storage)
     double rho_ref;        // rho0 (shifted) or 0: reference of the stored values
     double e2_ref;         // sum_q w_q rho_ref c_q^2 = 3 rho_ref theta0
     uint32_t* flag;        // set to 1 when a node has rho <= 0, theta <= 0 or NaN
     uint32_t xcd_remap;    // 1: group consecutive tiles per XCD
+    uint32_t step;         // step counter and seed of the stochastic rounding
+    uint32_t seed;
 };
+
+// Counter-based random bits for stochastic rounding: one hash per node and
+// step ("lowbias32", C. Wellons, hash-prospector), then Marsaglia's
+// xorshift32 (J. Stat. Softw. 8(14), 2003) for successive 32-bit words.
+__host__ __device__ inline uint32_t hash32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+__host__ __device__ inline uint32_t xorshift32(uint32_t& s)
+{
+    s ^= s << 13;
+    s ^= s >> 17;
+    s ^= s << 5;
+    return s;
+}
+
+// FP32 x + d rounded stochastically: s = RN(x + d) with exact residual e
+// (Fast2Sum, |x| >= |d|), then RN(s + e + (r - 1/2) ulp(s)) rounds the exact
+// sum up or down with probabilities given by its position between the two
+// neighbouring FP32 values (x > 0).
+__device__ inline float sr_add(float x, float d, uint32_t r16)
+{
+    const float s = x + d;
+    const float e = d - (s - x);
+    const float ulp = __uint_as_float(__float_as_uint(s) & 0x7f800000u) * 0x1p-23f;
+    const float z = fmaf(fmaf(float(r16 & 0xffffu), 0x1p-16f, -0.5f), ulp, e);
+    return s + z;
+}
 
 }  // namespace lbm

@@ -28,6 +28,92 @@ __device__ inline void flag_bad(const StepParams& p, R rho, R theta)
 }
 
 // ---------------------------------------------------------------------------
+// Collision of one node (Sec. II: f* = f + omega (f_eq - f); Sec. V: f_eq the
+// entropic equilibrium of the node's rho, j, E) on its stored values x_q:
+// f_q for direct storage, h_q = (f_q - w_q rho0) 2^{k_q} for the shifted
+// forms. Returns in y the new stored values h* for the shifted forms and
+// the increment f* - f for direct storage (before rounding to the storage
+// type), and rho and theta for the realisability flag.
+//
+// Moments are formed from deviations from the reference state w_q rho_ref:
+// for direct storage d_q = f_q - w_q (exact in floating point while f_q is
+// within a factor two of w_q), for shifted storage the stored h_q scaled
+// per shell. The relaxation is folded into one or two fused multiply-adds
+// per population with omega w_s rho_ref (and the storage scale) per shell.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct CollideConst {
+    R om;            // omega
+    R rho_ref;       // rho0 (shifted storage) or 1
+    R inv_scale[6];  // 2^{-k_s} (shifted) or 1
+    R omw[6];        // omega w_s rho_ref 2^{k_s} (shifted) or omega w_s
+};
+
+template <typename R, bool SHIFTED, int NEWTON>
+__host__ __device__ inline void collide(const R x[Q], R y[Q], const CollideConst<R>& cc, R& rho_out, R& theta_out)
+{
+    ShellSums<R> SS;
+    if constexpr (SHIFTED) {
+        shell_sums<R>(x, SS);
+    } else {
+        R d[Q];
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            d[q] = x[q] - R(weight(q));
+        });
+        shell_sums<R>(d, SS);
+    }
+    NodeDev<R> st;
+    st.rho_ref = cc.rho_ref;
+    R drho = R(0), jx = R(0), jy = R(0), jz = R(0), de2 = R(0);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        const R s0 = cc.inv_scale[s] * SS.s0[s];
+        drho += s0;
+        if (s == 0) continue;
+        de2 += R(SHELL_C2[s]) * s0;
+        const R kc = cc.inv_scale[s] * R(SHELL_CA[s]);
+        jx += kc * SS.sx[s];
+        jy += kc * SS.sy[s];
+        jz += kc * SS.sz[s];
+    }
+    st.drho = drho;
+    st.j[0] = jx;
+    st.j[1] = jy;
+    st.j[2] = jz;
+    st.de2 = de2;
+    st.rho = st.rho_ref * R(SUM_W) + drho;
+    st.irho = R(1) / st.rho;
+    const R ux = jx * st.irho, uy = jy * st.irho, uz = jz * st.irho;
+    const R K = (st.rho_ref * R(SUM_WC2) + de2) * st.irho;  // 2E/rho = u^2 + 3 theta
+    const R theta = (K - (ux * ux + uy * uy + uz * uz)) * R(1.0 / 3.0);
+    rho_out = st.rho;
+    theta_out = theta;
+
+    Mult<R> m;
+    const R ith = R(1) / theta;
+    m.b[0] = ux * ith;
+    m.b[1] = uy * ith;
+    m.b[2] = uz * ith;
+    m.g = R(0.5) * ith - R(0.5 / THETA0);
+#pragma unroll
+    for (int it = 0; it < NEWTON; ++it) newton_step<R>(m, st);
+
+    // f_eq,q - w_q rho_ref = w_q rho_ref D_q with 1 + D_q = (1 + eps_q)(1 + kappa)
+    Shells<R> S;
+    shells_at<R>(m, S);
+    const R kap = kappa_of<R>(st, S);
+    const R om = cc.om, om1 = R(1) - om;
+    static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int sh = VEL[q].shell;
+        const R D = dmul(gibbs_dev<q, R>(S), kap);
+        if constexpr (SHIFTED) y[q] = fma(om1, x[q], cc.omw[sh] * D);                // h* = (1-w) h + w 2^k d_eq
+        else y[q] = fma(cc.omw[sh], D, -om * (x[q] - R(weight(q))));                  // f* - f = w (f_eq - f)
+    });
+}
+
+// ---------------------------------------------------------------------------
 // Fused step: pull the 41 populations of a node along the links (Sec. IV,
 // periodic), form rho, j, E (Sec. II), solve the entropic equilibrium
 // (Sec. V), relax with the BGK rate omega (Sec. II) and store the
@@ -35,12 +121,6 @@ __device__ inline void flag_bad(const StepParams& p, R rho, R theta)
 // thread; every load and store is coalesced along x. Addresses are a
 // per-q scalar base plus a 32-bit byte offset.
 //
-// Moments are formed from deviations from the reference state w_q rho_k:
-// for direct storage d_q = f_q - w_q (exact in floating point while f_q is
-// within a factor two of w_q), for shifted storage the stored h_q scaled
-// per shell. Relaxation f* = (1 - omega) f + omega f_eq is folded into one
-// fused multiply-add per population, with omega rho/Z (and the storage
-// scale) folded into the six shell prefactors of f_eq.
 // ---------------------------------------------------------------------------
 // Launch variants (block size, cache-policy hints); the per-node arithmetic
 // is the same in every variant, so results do not depend on the choice.
@@ -75,7 +155,7 @@ __device__ inline void st_hint(T* p, T v, int nt)
     }
 }
 
-template <class ST, int NEWTON, int BLK, int FL>
+template <class ST, int NEWTON, int BLK, int FL, bool SR>
 __global__ __launch_bounds__(BLK) void k_step(const typename ST::T* __restrict__ fin,
                                               typename ST::T* __restrict__ fout, StepParams p)
 {
@@ -98,71 +178,33 @@ __global__ __launch_bounds__(BLK) void k_step(const typename ST::T* __restrict__
                                   FL & FL_NT_LOAD));
     });
 
-    ShellSums<R> S;
-    R rho_k, e2_k;
-    if constexpr (ST::shifted) {
-        shell_sums<R>(x, S);
-        rho_k = R(p.rho_ref);
-        e2_k = R(p.e2_ref);
-    } else {
-        R d[Q];
-        static_for<Q>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            d[q] = x[q] - R(weight(q));
-        });
-        shell_sums<R>(d, S);
-        rho_k = R(1);
-        e2_k = R(3.0 * THETA0);
-    }
-    R drho = R(0), jx = R(0), jy = R(0), jz = R(0), de2 = R(0);
+    CollideConst<R> cc;
+    cc.om = R(p.omega);
+    cc.rho_ref = ST::shifted ? R(p.rho_ref) : R(1);
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-        R k = R(1);
-        if constexpr (ST::shifted) k = R(p.inv_scale[s]);
-        const R s0 = k * S.s0[s];
-        drho += s0;
-        if (s == 0) continue;
-        de2 += R(SHELL_C2[s]) * s0;
-        const R kc = k * R(SHELL_CA[s]);
-        jx += kc * S.sx[s];
-        jy += kc * S.sy[s];
-        jz += kc * S.sz[s];
+        cc.inv_scale[s] = ST::unit_scale ? R(1) : R(p.inv_scale[s]);
+        cc.omw[s] = ST::shifted ? R(p.omw[s]) : cc.om * R(SHELL_W[s]);
     }
-    const R rho = rho_k + drho;
-    const R irho = R(1) / rho;
-    const R ux = jx * irho, uy = jy * irho, uz = jz * irho;
-    const R K = (e2_k + de2) * irho;  // 2E/rho = u^2 + 3 theta
-    const R u2 = ux * ux + uy * uy + uz * uz;
-    const R theta = (K - u2) * R(1.0 / 3.0);
+    R y[Q], rho, theta;
+    collide<R, ST::shifted, NEWTON>(x, y, cc, rho, theta);
     flag_bad<R>(p, rho, theta);
-
-    Mult<R> m;
-    const R ith = R(1) / theta;
-    m.b[0] = ux * ith;
-    m.b[1] = uy * ith;
-    m.b[2] = uz * ith;
-    m.g = R(0.5) * ith - R(0.5 / THETA0);
-#pragma unroll
-    for (int it = 0; it < NEWTON; ++it) newton_step<R>(m, ux, uy, uz, K);
-
-    Gibbs<R> G;
-    gibbs_factors<R>(m, G);
-    const R om = R(p.omega), om1 = R(1) - om;
-    const R oa = om * rho / G.Z;
-    R P[6];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-        P[s] = oa * G.T[s];
-        if constexpr (ST::shifted) P[s] *= R(p.scale[s]);
-    }
     const uint32_t nbytes = n * uint32_t(sizeof(T));
+    uint32_t rs = 0, rw = 0;
+    if constexpr (SR) rs = hash32(n ^ hash32(p.step * 0x9e3779b9u + p.seed)) | 1u;
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        const R e = gibbs_term<q, R>(G, P);
-        R v;
-        if constexpr (ST::shifted) v = fma(om1, x[q], e + R(p.cshift[VEL[q].shell]));
-        else v = fma(om1, x[q], e);
-        st_hint(reinterpret_cast<T*>(dst + q * qbytes + uint64_t(nbytes)), ST::encode(v), FL & FL_NT_STORE);
+        T out;
+        if constexpr (SR) {
+            if constexpr (q % 2 == 0) rw = xorshift32(rs);
+            const uint32_t rb = (q % 2 == 0) ? (rw & 0xffffu) : (rw >> 16);
+            if constexpr (ST::shifted) out = ST::encode_sr(y[q], rb);
+            else out = sr_add(x[q], y[q], rb);
+        } else {
+            if constexpr (ST::shifted) out = ST::encode(y[q]);
+            else out = ST::encode(x[q] + y[q]);
+        }
+        st_hint(reinterpret_cast<T*>(dst + q * qbytes + uint64_t(nbytes)), out, FL & FL_NT_STORE);
     });
 }
 
@@ -173,23 +215,33 @@ __global__ __launch_bounds__(BLK) void k_step(const typename ST::T* __restrict__
 // ---------------------------------------------------------------------------
 constexpr int INIT_NEWTON = 6;
 
-__device__ inline void equilibrium_f64(double rho, double ux, double uy, double uz, double theta, double e[Q],
-                                       double& a)
+// Deviations D_q (f_eq,q = w_q rho_ref (1 + D_q)) of the equilibrium of
+// (rho, u, theta) in FP64, relative to the reference state w_q rho_ref.
+__device__ inline void equilibrium_dev_f64(double rho, double ux, double uy, double uz, double theta,
+                                           double rho_ref, double D[Q])
 {
-    const double K = ux * ux + uy * uy + uz * uz + 3.0 * theta;
+    NodeDev<double> st;
+    st.rho_ref = rho_ref;
+    st.rho = rho;
+    st.irho = 1.0 / rho;
+    st.drho = rho - rho_ref * SUM_W;
+    st.j[0] = rho * ux;
+    st.j[1] = rho * uy;
+    st.j[2] = rho * uz;
+    st.de2 = rho * (ux * ux + uy * uy + uz * uz + 3.0 * theta) - rho_ref * SUM_WC2;
     Mult<double> m;
     m.b[0] = ux / theta;
     m.b[1] = uy / theta;
     m.b[2] = uz / theta;
     m.g = 0.5 / theta - 0.5 / THETA0;
-    for (int it = 0; it < INIT_NEWTON; ++it) newton_step<double>(m, ux, uy, uz, K);
-    Gibbs<double> G;
-    gibbs_factors<double>(m, G);
+    for (int it = 0; it < INIT_NEWTON; ++it) newton_step<double>(m, st);
+    Shells<double> S;
+    shells_at<double>(m, S);
+    const double kap = kappa_of<double>(st, S);
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        e[q] = gibbs_term<q, double>(G, G.T);
+        D[q] = dmul(gibbs_dev<q, double>(S), kap);
     });
-    a = rho / G.Z;
 }
 
 __device__ inline void block_max_float(float v, float* out)
@@ -217,19 +269,22 @@ __global__ __launch_bounds__(BLOCK) void k_init(typename ST::T* __restrict__ f, 
     if (i < count) {
         const double rho = fields[i], ux = fields[count + i], uy = fields[2 * count + i],
                      uz = fields[3 * count + i], th = fields[4 * count + i];
-        double e[Q], a;
-        equilibrium_f64(rho, ux, uy, uz, th, e, a);
-        bool bad = !(a > 0.0) || !(a < 1e300);
+        // storage reference: rho0 for the shifted forms, the weights themselves otherwise
+        const double rref = ST::shifted ? p.rho_ref : 1.0;
+        double D[Q];
+        equilibrium_dev_f64(rho, ux, uy, uz, th, rref, D);
+        bool bad = false;
         static_for<Q>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             constexpr int sh = VEL[q].shell;
-            const double d = a * e[q] - SHELL_W[sh] * p.rho_ref;
-            bad |= !(fabs(d) < 1e300);
+            const double d = SHELL_W[sh] * rref * D[q];  // f_eq,q - w_q rref
+            bad |= !(fabs(d) < 1e300) || !(SHELL_W[sh] * rref + d > 0.0);
             if (mode == 0) {
                 dev = fmaxf(dev, float(fabs(d) * double(1u << SHELL_K[sh])));
             } else {
-                double v = d;
-                if constexpr (ST::shifted) v *= double(p.scale[sh]);
+                double v;
+                if constexpr (ST::shifted) v = d * double(p.scale[sh]);
+                else v = SHELL_W[sh] + d;
                 ST::store(f + size_t(q) * N + n0 + i, typename ST::R(v));
             }
         });
@@ -284,25 +339,28 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const typename ST::T* __restr
     for (int k = 0; k < 5; ++k) out[size_t(k) * count + i] = m[k];
 }
 
-// Block-wide FP64 sum of 5 values: wavefront butterfly (64 lanes), then the
-// 4 wave partials in LDS. Result valid in thread 0.
-__device__ inline void block_sum5(double v[5], double out[5])
+// Block-wide FP64 sum of K values: wavefront butterfly (64 lanes), then the
+// wave partials in LDS. Result valid in thread 0.
+template <int K>
+__device__ inline void block_sum(double v[K], double out[K])
 {
 #pragma unroll
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < K; ++k)
         for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
-    __shared__ double sm[BLOCK / 64][5];
+    __shared__ double sm[BLOCK / 64][K];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0)
-        for (int k = 0; k < 5; ++k) sm[wv][k] = v[k];
+        for (int k = 0; k < K; ++k) sm[wv][k] = v[k];
     __syncthreads();
     if (threadIdx.x == 0)
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < K; ++k) {
             double s = sm[0][k];
             for (int i = 1; i < BLOCK / 64; ++i) s += sm[i][k];
             out[k] = s;
         }
 }
+
+__device__ inline void block_sum5(double v[5], double out[5]) { block_sum<5>(v, out); }
 
 constexpr int TOTAL_BLOCKS = 1024;
 
@@ -320,21 +378,57 @@ __global__ __launch_bounds__(BLOCK) void k_totals(const typename ST::T* __restri
         for (int k = 0; k < 5; ++k) acc[k] += m[k];
     }
     double r[5];
-    block_sum5(acc, r);
+    block_sum<5>(acc, r);
     if (threadIdx.x == 0)
         for (int k = 0; k < 5; ++k) partials[blockIdx.x * 5 + k] = r[k];
 }
 
+template <int K>
 __global__ __launch_bounds__(BLOCK) void k_reduce_partials(const double* __restrict__ partials, uint32_t nblk,
                                                            double* __restrict__ out)
 {
-    double acc[5] = {0, 0, 0, 0, 0};
+    double acc[K];
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
     for (uint32_t b = threadIdx.x; b < nblk; b += BLOCK)
-        for (int k = 0; k < 5; ++k) acc[k] += partials[b * 5 + k];
-    double r[5];
-    block_sum5(acc, r);
+        for (int k = 0; k < K; ++k) acc[k] += partials[b * K + k];
+    double r[K];
+    block_sum<K>(acc, r);
     if (threadIdx.x == 0)
-        for (int k = 0; k < 5; ++k) out[k] = r[k];
+        for (int k = 0; k < K; ++k) out[k] = r[k];
+}
+
+// Fourier amplitudes (1/N) sum_n m(n) e^{-i k.x_n} of rho, jx, jy, jz, E and
+// theta = (2E/rho - u^2)/3 at the true node positions (sublattice 1 at
+// +1/2 in every direction): per-block partial sums of 12 values.
+constexpr int PROJ_FIELDS = 6;
+
+template <class ST>
+__global__ __launch_bounds__(BLOCK) void k_project(const typename ST::T* __restrict__ f, StepParams p, double kx,
+                                                   double ky, double kz, double* __restrict__ partials)
+{
+    const uint32_t N = p.g.N;
+    double acc[2 * PROJ_FIELDS];
+    for (int k = 0; k < 2 * PROJ_FIELDS; ++k) acc[k] = 0.0;
+    for (uint32_t n = blockIdx.x * BLOCK + threadIdx.x; n < N; n += gridDim.x * BLOCK) {
+        double m[5];
+        node_moments64<ST>(f, N, n, p, m);
+        const Coord c = decode(n, p.g);
+        const double h = 0.5 * double(c.s);
+        const double ph = kx * (double(c.x) + h) + ky * (double(c.y) + h) + kz * (double(c.z) + h);
+        double sn, cs;
+        sincos(ph, &sn, &cs);
+        const double u2 = (m[1] * m[1] + m[2] * m[2] + m[3] * m[3]) / (m[0] * m[0]);
+        const double th = (2.0 * m[4] / m[0] - u2) / 3.0;
+        const double v[PROJ_FIELDS] = {m[0], m[1], m[2], m[3], m[4], th};
+        for (int k = 0; k < PROJ_FIELDS; ++k) {
+            acc[2 * k] += v[k] * cs;
+            acc[2 * k + 1] -= v[k] * sn;
+        }
+    }
+    double r[2 * PROJ_FIELDS];
+    block_sum<2 * PROJ_FIELDS>(acc, r);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 2 * PROJ_FIELDS; ++k) partials[blockIdx.x * 2 * PROJ_FIELDS + k] = r[k];
 }
 
 // ---------------------------------------------------------------------------

@@ -59,6 +59,22 @@ constexpr double theta0_value()
 }
 constexpr double THETA0 = theta0_value();
 
+// sum_i w_i and sum_i w_i c_i^2 (= 1 and 3 theta0 up to rounding)
+constexpr double sum_w_value()
+{
+    double s = 0.0;
+    for (int q = 0; q < Q; ++q) s += weight(q);
+    return s;
+}
+constexpr double sum_wc2_value()
+{
+    double s = 0.0;
+    for (int q = 0; q < Q; ++q) s += weight(q) * 0.25 * (VEL[q].x * VEL[q].x + VEL[q].y * VEL[q].y + VEL[q].z * VEL[q].z);
+    return s;
+}
+constexpr double SUM_W = sum_w_value();
+constexpr double SUM_WC2 = sum_wc2_value();
+
 // Power-of-two exponent per shell used by the shifted storage so that
 // (f - w rho0) 2^k has magnitude ~ (relative deviation) 2^k_amp:
 // k_shell = round(-log2 w_shell).

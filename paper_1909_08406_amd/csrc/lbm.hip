@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -31,7 +32,8 @@ int elem_bytes(int storage)
 {
     switch (storage) {
         case LBM_F64: return 8;
-        case LBM_F32: return 4;
+        case LBM_F32:
+        case LBM_F32_SHIFT: return 4;
         case LBM_F16_SHIFT:
         case LBM_BF16_SHIFT: return 2;
         default: return 0;
@@ -59,7 +61,10 @@ int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
     if (eb == 0) return LBM_E_ARG;
     if (opts->tau_conv != LBM_TAU_LB && opts->tau_conv != LBM_TAU_PAPER) return LBM_E_ARG;
     if (opts->newton_iters < 0 || opts->newton_iters > 4) return LBM_E_ARG;
-    if (opts->reserved != 0 || opts->flags != 0) return LBM_E_ARG;
+    if (opts->flags & ~uint32_t(LBM_FLAG_STOCHASTIC_ROUNDING)) return LBM_E_ARG;
+    if ((opts->flags & LBM_FLAG_STOCHASTIC_ROUNDING) &&
+        !(opts->storage == LBM_F32 || opts->storage == LBM_F16_SHIFT || opts->storage == LBM_BF16_SHIFT))
+        return LBM_E_ARG;
     if (!(opts->rho0 >= 0.0) || !std::isfinite(opts->rho0)) return LBM_E_ARG;
     if (opts->shift_exp != LBM_SHIFT_AUTO && (opts->shift_exp < -60 || opts->shift_exp > 60)) return LBM_E_ARG;
     for (int b = 0; b < nboxes; ++b) {
@@ -87,7 +92,8 @@ Layout plan(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
     L.buf_bytes = align_up(L.elems * eb);
     L.flag_off = 2 * L.buf_bytes;
     L.partial_off = L.flag_off + ALIGN;
-    L.staging_off = L.partial_off + align_up(uint64_t(TOTAL_BLOCKS) * 5 * sizeof(double) + 5 * sizeof(double));
+    // partial sums: up to TOTAL_BLOCKS blocks of 2*PROJ_FIELDS doubles, then the result
+    L.staging_off = L.partial_off + align_up(uint64_t(TOTAL_BLOCKS + 1) * 2 * PROJ_FIELDS * sizeof(double));
     // staging holds chunks of FP64 node fields (5 per node) or populations
     const uint64_t want = std::max<uint64_t>(L.max_nodes * 8 * uint64_t(Q), 4096);
     L.staging_bytes = align_up(std::min(want, STAGING_MAX));
@@ -115,6 +121,8 @@ struct lbm_ctx {
     char* staging = nullptr;
     int variant = 0;
     double rho_ref_storage = 0.0;  // rho0 for shifted storage, else 0
+    bool stochastic = false;       // stochastic rounding of the stored values
+    uint32_t steps_done = 0;       // counter feeding the stochastic rounding
 
     char* buf(int i) const { return mem + uint64_t(i) * L.buf_bytes; }
     StepParams params(const BoxDev& b) const
@@ -122,8 +130,10 @@ struct lbm_ctx {
         StepParams p = base;
         p.g = b.g;
         p.omega = b.omega;
+        p.step = steps_done;
+        // the kernel's reference weights are the FP32-rounded ones
         for (int s = 0; s < 6; ++s)
-            p.cshift[s] = float(-b.omega * double(SHELL_W[s]) * rho_ref_storage * double(p.scale[s]));
+            p.omw[s] = float(b.omega * double(float(SHELL_W[s])) * rho_ref_storage * double(p.scale[s]));
         return p;
     }
 };
@@ -143,6 +153,7 @@ int dispatch_storage(int storage, F&& f)
         case LBM_F32: return f(StoreF32{});
         case LBM_F16_SHIFT: return f(StoreF16S{});
         case LBM_BF16_SHIFT: return f(StoreBF16S{});
+        case LBM_F32_SHIFT: return f(StoreF32S{});
         default: return LBM_E_ARG;
     }
 }
@@ -160,27 +171,41 @@ constexpr VariantDesc VARIANTS[] = {
 };
 constexpr int NVARIANTS = int(sizeof(VARIANTS) / sizeof(VARIANTS[0]));
 
-template <class ST, int NEWTON, int BLK, int FL>
+template <class ST, int NEWTON, int BLK, int FL, bool SR>
 void launch_k(const BoxDev& b, hipStream_t st, const typename ST::T* in, typename ST::T* out, const StepParams& p)
 {
-    hipLaunchKernelGGL((k_step<ST, NEWTON, BLK, FL>), dim3(uint32_t((b.nodes + BLK - 1) / BLK)), dim3(BLK), 0, st, in,
-                       out, p);
+    hipLaunchKernelGGL((k_step<ST, NEWTON, BLK, FL, SR>), dim3(uint32_t((b.nodes + BLK - 1) / BLK)), dim3(BLK), 0,
+                       st, in, out, p);
 }
 
-template <class ST, int NEWTON>
+template <class ST, int NEWTON, bool SR>
 int launch_variant(int v, const BoxDev& b, hipStream_t st, const typename ST::T* in, typename ST::T* out,
                    const StepParams& p)
 {
     switch (v) {
-        case 0: launch_k<ST, NEWTON, 256, 0>(b, st, in, out, p); break;
-        case 1: launch_k<ST, NEWTON, 256, FL_NT_LOAD | FL_NT_STORE>(b, st, in, out, p); break;
-        case 2: launch_k<ST, NEWTON, 512, 0>(b, st, in, out, p); break;
-        case 3: launch_k<ST, NEWTON, 128, 0>(b, st, in, out, p); break;
-        case 4: launch_k<ST, NEWTON, 256, FL_NT_STORE>(b, st, in, out, p); break;
-        case 5: launch_k<ST, NEWTON, 1024, 0>(b, st, in, out, p); break;
+        case 0: launch_k<ST, NEWTON, 256, 0, SR>(b, st, in, out, p); break;
+        case 1: launch_k<ST, NEWTON, 256, FL_NT_LOAD | FL_NT_STORE, SR>(b, st, in, out, p); break;
+        case 2: launch_k<ST, NEWTON, 512, 0, SR>(b, st, in, out, p); break;
+        case 3: launch_k<ST, NEWTON, 128, 0, SR>(b, st, in, out, p); break;
+        case 4: launch_k<ST, NEWTON, 256, FL_NT_STORE, SR>(b, st, in, out, p); break;
+        case 5: launch_k<ST, NEWTON, 1024, 0, SR>(b, st, in, out, p); break;
         default: return LBM_E_ARG;
     }
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+}
+
+template <class ST, int NEWTON>
+int launch_newton(lbm_ctx* ctx, const BoxDev& b, const typename ST::T* in, typename ST::T* out,
+                  const StepParams& p)
+{
+    // stochastic rounding exists for the FP32-arithmetic forms whose
+    // rounding is coarse: FP32 of f, FP16 and BF16 of the shift
+    constexpr bool has_sr = std::is_same<ST, StoreF32>::value || std::is_same<ST, StoreF16S>::value ||
+                            std::is_same<ST, StoreBF16S>::value;
+    if constexpr (has_sr) {
+        if (ctx->stochastic) return launch_variant<ST, NEWTON, true>(ctx->variant, b, ctx->stream, in, out, p);
+    }
+    return launch_variant<ST, NEWTON, false>(ctx->variant, b, ctx->stream, in, out, p);
 }
 
 template <class ST>
@@ -188,10 +213,10 @@ int launch_step_typed(lbm_ctx* ctx, const BoxDev& b, const typename ST::T* in, t
 {
     const StepParams p = ctx->params(b);
     switch (ctx->newton) {
-        case 1: return launch_variant<ST, 1>(ctx->variant, b, ctx->stream, in, out, p);
-        case 2: return launch_variant<ST, 2>(ctx->variant, b, ctx->stream, in, out, p);
-        case 3: return launch_variant<ST, 3>(ctx->variant, b, ctx->stream, in, out, p);
-        case 4: return launch_variant<ST, 4>(ctx->variant, b, ctx->stream, in, out, p);
+        case 1: return launch_newton<ST, 1>(ctx, b, in, out, p);
+        case 2: return launch_newton<ST, 2>(ctx, b, in, out, p);
+        case 3: return launch_newton<ST, 3>(ctx, b, in, out, p);
+        case 4: return launch_newton<ST, 4>(ctx, b, in, out, p);
         default: return LBM_E_ARG;
     }
 }
@@ -238,13 +263,32 @@ int run_init(lbm_ctx* ctx, const BoxDev& b, uint64_t node_base, const double* co
 void set_shift(lbm_ctx* ctx)
 {
     for (int s = 0; s < 6; ++s) {
-        const int k = ctx->kamp + SHELL_K[s];
+        const int k = ctx->storage == LBM_F32_SHIFT ? 0 : ctx->kamp + SHELL_K[s];
         ctx->base.scale[s] = std::ldexp(1.0f, k);
         ctx->base.inv_scale[s] = std::ldexp(1.0f, -k);
     }
 }
 
 }  // namespace
+
+namespace {
+template <typename R, int NEWTON>
+void collide_host(double omega, const double* in, double* out)
+{
+    CollideConst<R> cc;
+    cc.om = R(omega);
+    cc.rho_ref = R(1);
+    for (int s = 0; s < 6; ++s) {
+        cc.inv_scale[s] = R(1);
+        cc.omw[s] = cc.om * R(SHELL_W[s]);
+    }
+    R x[Q], y[Q], rho, theta;
+    for (int q = 0; q < Q; ++q) x[q] = R(in[q]);
+    collide<R, false, NEWTON>(x, y, cc, rho, theta);
+    for (int q = 0; q < Q; ++q) out[q] = double(R(x[q] + y[q]));
+}
+}  // namespace
+
 
 extern "C" {
 
@@ -287,7 +331,9 @@ int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts
     ctx->newton = opts->newton_iters ? opts->newton_iters : (opts->storage == LBM_F64 ? 3 : 1);
     ctx->rho0 = opts->rho0 > 0 ? opts->rho0 : 1.0;
     ctx->L = plan(boxes, nboxes, opts);
-    const bool shifted = opts->storage == LBM_F16_SHIFT || opts->storage == LBM_BF16_SHIFT;
+    ctx->stochastic = (opts->flags & LBM_FLAG_STOCHASTIC_ROUNDING) != 0;
+    const bool shifted = opts->storage == LBM_F16_SHIFT || opts->storage == LBM_BF16_SHIFT ||
+                         opts->storage == LBM_F32_SHIFT;
 
     uint64_t off = 0;
     for (int b = 0; b < nboxes; ++b) {
@@ -340,6 +386,7 @@ int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts
 
     ctx->base.flag = ctx->flag;
     ctx->base.xcd_remap = 1;
+    ctx->base.seed = opts->seed;
     ctx->base.rho_ref = shifted ? ctx->rho0 : 0.0;
     ctx->rho_ref_storage = ctx->base.rho_ref;
     double e2 = 0.0;  // sum_q w_q c_q^2 rho_ref
@@ -352,7 +399,7 @@ int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts
     if (hipMemsetAsync(ctx->flag, 0, ALIGN, ctx->stream) != hipSuccess) return fail(LBM_E_HIP);
     const double* fields[5] = {rho, ux, uy, uz, theta};
 
-    if (shifted) {
+    if (shifted && ctx->storage != LBM_F32_SHIFT) {
         if (opts->shift_exp == LBM_SHIFT_AUTO) {
             // largest |f - w rho0| 2^k_shell of the initial state, then k_amp
             // so that it becomes about 2^10 (FP16 max is 65504: ~64x headroom)
@@ -397,6 +444,7 @@ int lbm_step(lbm_ctx* ctx, int32_t n)
             if (rc) return rc;
         }
         ctx->cur ^= 1;
+        ++ctx->steps_done;
     }
     return LBM_OK;
 }
@@ -450,7 +498,7 @@ int lbm_status(lbm_ctx* ctx)
 int lbm_totals(lbm_ctx* ctx, double* out)
 {
     if (!ctx || !out) return LBM_E_ARG;
-    double* res = ctx->partials + TOTAL_BLOCKS * 5;
+    double* res = ctx->partials + TOTAL_BLOCKS * 2 * PROJ_FIELDS;
     for (size_t bi = 0; bi < ctx->boxes.size(); ++bi) {
         const BoxDev& b = ctx->boxes[bi];
         const StepParams p = ctx->params(b);
@@ -461,7 +509,7 @@ int lbm_totals(lbm_ctx* ctx, double* out)
             const T* f = reinterpret_cast<const T*>(ctx->buf(ctx->cur)) + b.offset;
             hipLaunchKernelGGL((k_totals<ST>), dim3(nblk), dim3(BLOCK), 0, ctx->stream, f, uint32_t(b.nodes), p,
                                ctx->partials);
-            hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->partials, nblk, res);
+            hipLaunchKernelGGL(k_reduce_partials<5>, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->partials, nblk, res);
             return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
         });
         if (rc) return rc;
@@ -469,6 +517,30 @@ int lbm_totals(lbm_ctx* ctx, double* out)
         HIPCHK(hipStreamSynchronize(ctx->stream));
     }
     return lbm_status(ctx);
+}
+
+int lbm_project(lbm_ctx* ctx, int32_t box, const double* k, double* out)
+{
+    if (!ctx || !k || !out || box < 0 || box >= int32_t(ctx->boxes.size())) return LBM_E_ARG;
+    const BoxDev& b = ctx->boxes[box];
+    const StepParams p = ctx->params(b);
+    const uint32_t nblk = std::min<uint32_t>(TOTAL_BLOCKS, nblocks(b.nodes));
+    double* res = ctx->partials + TOTAL_BLOCKS * 2 * PROJ_FIELDS;
+    int rc = dispatch_storage(ctx->storage, [&](auto st) {
+        using ST = decltype(st);
+        using T = typename ST::T;
+        const T* f = reinterpret_cast<const T*>(ctx->buf(ctx->cur)) + b.offset;
+        hipLaunchKernelGGL((k_project<ST>), dim3(nblk), dim3(BLOCK), 0, ctx->stream, f, p, k[0], k[1], k[2],
+                           ctx->partials);
+        hipLaunchKernelGGL(k_reduce_partials<2 * PROJ_FIELDS>, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->partials,
+                           nblk, res);
+        return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+    });
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(out, res, 2 * PROJ_FIELDS * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < 2 * PROJ_FIELDS; ++i) out[i] /= double(b.nodes);
+    return LBM_OK;
 }
 
 int lbm_get_populations(lbm_ctx* ctx, double* f)
@@ -581,6 +653,13 @@ int lbm_debug_pull_map(lbm_ctx* ctx, int32_t box, int64_t* src)
     return LBM_OK;
 }
 
+int lbm_set_step_counter(lbm_ctx* ctx, uint32_t steps_done)
+{
+    if (!ctx) return LBM_E_ARG;
+    ctx->steps_done = steps_done;
+    return LBM_OK;
+}
+
 int lbm_get_info(lbm_ctx* ctx, lbm_info* info)
 {
     if (!ctx || !info) return LBM_E_ARG;
@@ -588,6 +667,8 @@ int lbm_get_info(lbm_ctx* ctx, lbm_info* info)
     info->storage = ctx->storage;
     info->newton_iters = ctx->newton;
     info->shift_exp = (ctx->storage == LBM_F16_SHIFT || ctx->storage == LBM_BF16_SHIFT) ? ctx->kamp : 0;
+    info->flags = ctx->stochastic ? LBM_FLAG_STOCHASTIC_ROUNDING : 0u;
+    info->steps_done = ctx->steps_done;
     info->nboxes = int32_t(ctx->boxes.size());
     info->nodes = int64_t(ctx->L.elems / Q);
     info->bytes_per_step = int64_t(2 * ctx->L.elems * uint64_t(elem_bytes(ctx->storage)));
@@ -698,6 +779,29 @@ const char* lbm_strerror(int code)
         case LBM_E_UNSUPPORTED: return "unsupported request";
         default: return "unknown error";
     }
+}
+
+int lbm_collide_host(int32_t precision, int32_t newton, double omega, const double* f_in, double* f_out)
+{
+    if (!f_in || !f_out || (precision != 0 && precision != 1) || newton < 0 || newton > 4) return LBM_E_ARG;
+    if (precision == 0) {
+        switch (newton) {
+            case 0: collide_host<double, 0>(omega, f_in, f_out); break;
+            case 1: collide_host<double, 1>(omega, f_in, f_out); break;
+            case 2: collide_host<double, 2>(omega, f_in, f_out); break;
+            case 3: collide_host<double, 3>(omega, f_in, f_out); break;
+            default: collide_host<double, 4>(omega, f_in, f_out); break;
+        }
+    } else {
+        switch (newton) {
+            case 0: collide_host<float, 0>(omega, f_in, f_out); break;
+            case 1: collide_host<float, 1>(omega, f_in, f_out); break;
+            case 2: collide_host<float, 2>(omega, f_in, f_out); break;
+            case 3: collide_host<float, 3>(omega, f_in, f_out); break;
+            default: collide_host<float, 4>(omega, f_in, f_out); break;
+        }
+    }
+    return LBM_OK;
 }
 
 int lbm_selftest(void)

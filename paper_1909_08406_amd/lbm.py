@@ -14,10 +14,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 NQ = 41
-F64, F32, F16_SHIFT, BF16_SHIFT = 0, 1, 2, 3
+F64, F32, F16_SHIFT, BF16_SHIFT, F32_SHIFT = 0, 1, 2, 3, 4
+FLAG_STOCHASTIC_ROUNDING = 1
 TAU_LB, TAU_PAPER = 0, 1
 SHIFT_AUTO = -1000
-STORAGE = {"f64": F64, "f32": F32, "f16s": F16_SHIFT, "bf16s": BF16_SHIFT}
+STORAGE = {"f64": F64, "f32": F32, "f16s": F16_SHIFT, "bf16s": BF16_SHIFT, "f32s": F32_SHIFT}
+ELEM_BYTES = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2, "f32s": 4}
 
 OK, E_ARG, E_NOMEM, E_DOMAIN, E_NONFINITE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 
@@ -36,13 +38,14 @@ class Box(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("storage", ctypes.c_int32), ("tau_conv", ctypes.c_int32), ("rho0", ctypes.c_double),
                 ("newton_iters", ctypes.c_int32), ("shift_exp", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32)]
+                ("seed", ctypes.c_uint32)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("storage", ctypes.c_int32), ("newton_iters", ctypes.c_int32), ("shift_exp", ctypes.c_int32),
                 ("nboxes", ctypes.c_int32), ("nodes", ctypes.c_int64), ("bytes_per_step", ctypes.c_int64),
-                ("block_threads", ctypes.c_int32), ("variant", ctypes.c_int32), ("device_bytes", ctypes.c_uint64)]
+                ("block_threads", ctypes.c_int32), ("variant", ctypes.c_int32), ("device_bytes", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("steps_done", ctypes.c_uint32)]
 
 
 class Tuning(ctypes.Structure):
@@ -65,11 +68,13 @@ SIGNATURES = {
     "lbm_moments": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
     "lbm_totals": (ctypes.c_int, [_vp, _dp]),
     "lbm_status": (ctypes.c_int, [_vp]),
+    "lbm_project": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp]),
     "lbm_get_populations": (ctypes.c_int, [_vp, _dp]),
     "lbm_set_populations": (ctypes.c_int, [_vp, _dp]),
     "lbm_gather": (ctypes.c_int, [_vp, ctypes.c_int32, _lp, ctypes.c_int64, _dp]),
     "lbm_debug_pull_map": (ctypes.c_int, [_vp, ctypes.c_int32, _lp]),
     "lbm_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
+    "lbm_set_step_counter": (ctypes.c_int, [_vp, ctypes.c_uint32]),
     "lbm_num_variants": (ctypes.c_int, []),
     "lbm_variant_desc": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_uint32)]),
@@ -80,6 +85,7 @@ SIGNATURES = {
     "lbm_free": (None, [_vp]),
     "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "lbm_selftest": (ctypes.c_int, []),
+    "lbm_collide_host": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _dp, _dp]),
 }
 
 _lib = None
@@ -127,15 +133,17 @@ def _boxes(boxes):
     return arr
 
 
-def _opts(storage, tau_conv, rho0, newton_iters, shift_exp):
+def _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic=False, seed=0):
     st = STORAGE[storage] if isinstance(storage, str) else int(storage)
     return Opts(st, int(tau_conv), float(rho0), int(newton_iters),
-                SHIFT_AUTO if shift_exp is None else int(shift_exp), 0, 0)
+                SHIFT_AUTO if shift_exp is None else int(shift_exp),
+                FLAG_STOCHASTIC_ROUNDING if stochastic else 0, int(seed) & 0xffffffff)
 
 
-def workspace_size(boxes, storage="f32", tau_conv=TAU_LB, rho0=1.0, newton_iters=0, shift_exp=None):
+def workspace_size(boxes, storage="f32", tau_conv=TAU_LB, rho0=1.0, newton_iters=0, shift_exp=None,
+                   stochastic=False):
     bx = _boxes(boxes)
-    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp)
+    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic)
     out = ctypes.c_uint64(0)
     _check(lib().lbm_workspace_size(bx, len(boxes), ctypes.byref(op), ctypes.byref(out)), "lbm_workspace_size")
     return int(out.value)
@@ -181,6 +189,14 @@ class Context:
     def status(self):
         return int(lib().lbm_status(self.handle))
 
+    def project(self, box, k):
+        """Complex Fourier amplitudes of (rho, jx, jy, jz, E, theta) of one box
+        at wavevector k (radians per cell), computed on the device."""
+        kv = np.ascontiguousarray(k, dtype=np.float64).reshape(3)
+        out = np.zeros(12)
+        _check(lib().lbm_project(self.handle, int(box), _d(kv), _d(out)), "lbm_project")
+        return out[0::2] + 1j * out[1::2]
+
     def get_populations(self):
         f = np.zeros(NQ * self.nodes)
         _check(lib().lbm_get_populations(self.handle, _d(f)), "lbm_get_populations")
@@ -203,6 +219,9 @@ class Context:
         out = np.zeros(NQ * n, dtype=np.int64)
         _check(lib().lbm_debug_pull_map(self.handle, int(box), out.ctypes.data_as(_lp)), "lbm_debug_pull_map")
         return out.reshape(NQ, n)
+
+    def set_step_counter(self, n):
+        _check(lib().lbm_set_step_counter(self.handle, int(n)), "lbm_set_step_counter")
 
     def info(self):
         i = Info()
@@ -244,13 +263,13 @@ class Context:
 
 
 def init(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0, newton_iters=0,
-         shift_exp=None, stream=None, torch_workspace=True):
+         shift_exp=None, stream=None, torch_workspace=True, stochastic=False, seed=0):
     """lbm_init. boxes: [(nx, ny, nz, tau), ...]; nodal FP64 fields of all
     boxes concatenated (theta absolute). stream: a torch.cuda.Stream (or
     None for the library's own). With torch_workspace the device memory is a
     torch uint8 tensor held by the returned Context."""
     bx = _boxes(boxes)
-    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp)
+    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, seed)
     arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (rho, ux, uy, uz, theta)]
     nodes = sum(2 * b[0] * b[1] * b[2] for b in boxes)
     for a in arrs:
@@ -260,7 +279,7 @@ def init(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0
     ws_ptr, ws_bytes = None, 0
     if torch_workspace:
         import torch
-        ws_bytes = workspace_size(boxes, storage, tau_conv, rho0, newton_iters, shift_exp)
+        ws_bytes = workspace_size(boxes, storage, tau_conv, rho0, newton_iters, shift_exp, stochastic)
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
         ws_ptr = ws.data_ptr()
     sptr = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
@@ -273,6 +292,16 @@ def init(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0
 
 def selftest():
     return int(lib().lbm_selftest())
+
+
+def collide_host(f, omega, precision="f32", newton=None):
+    """The kernel's per-node collision run on the host (FP64 or FP32)."""
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(NQ)
+    out = np.zeros(NQ)
+    pr = {"f64": 0, "f32": 1}[precision]
+    nt = (3 if pr == 0 else 1) if newton is None else int(newton)
+    _check(lib().lbm_collide_host(pr, nt, float(omega), _d(f), _d(out)), "lbm_collide_host")
+    return out
 
 
 def num_variants():

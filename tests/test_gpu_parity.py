@@ -188,22 +188,28 @@ def test_fp64_conservation_and_totals(L, orc, case, tol):
     assert np.max(np.abs(t0 - ref) / scale) < 1e-13
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
-def test_checkpoint_resume_is_bit_identical(L, storage):
+STORAGE_FORMS = [("f64", False), ("f32", False), ("f32", True), ("f32s", False), ("f16s", False), ("f16s", True),
+                 ("bf16s", False), ("bf16s", True)]
+
+
+@pytest.mark.parametrize("storage,sr", STORAGE_FORMS)
+def test_checkpoint_resume_is_bit_identical(L, storage, sr):
     dims, tau = (9, 6, 4), 0.58
-    say("checkpoint", storage)
+    say("checkpoint", storage, "stochastic rounding" if sr else "")
     F = wl.random_state(*dims, seed=12, amp_u=0.03, amp_rho=1e-3, amp_theta=1e-3)
     _, _, th = L.lattice()
-    a = L.init([(*dims, tau)], *F.absolute(th), storage=storage)
+    a = L.init([(*dims, tau)], *F.absolute(th), storage=storage, stochastic=sr)
     a.step(10)
     ref = a.get_populations()
     a.free()
-    b = L.init([(*dims, tau)], *F.absolute(th), storage=storage)
+    b = L.init([(*dims, tau)], *F.absolute(th), storage=storage, stochastic=sr)
     b.step(4)
     snap = b.get_populations()
+    steps = b.info()["steps_done"]
     b.free()
-    c = L.init([(*dims, tau)], *F.absolute(th), storage=storage)
+    c = L.init([(*dims, tau)], *F.absolute(th), storage=storage, stochastic=sr)
     c.set_populations(snap)
+    c.set_step_counter(steps)
     c.step(6)
     got = c.get_populations()
     c.free()
@@ -243,13 +249,15 @@ def test_nonfinite_state_is_flagged(L):
     ctx.free()
 
 
-@pytest.mark.parametrize("storage", ["f16s", "bf16s"])
-def test_shifted_storage_error_vs_fp64(L, orc, storage):
-    """Shifted 16-bit storage of f - w rho0 with FP32 arithmetic, against the
-    FP64 oracle on the 32x16x16 standing wave after 200 steps."""
+@pytest.mark.parametrize("storage,sr", [("f16s", False), ("f16s", True), ("bf16s", False), ("bf16s", True),
+                                       ("f32s", False), ("f32", True)])
+def test_shifted_storage_error_vs_fp64(L, orc, storage, sr):
+    """Shifted storage of f - w rho0 (and FP32 with stochastic rounding) with
+    FP32 arithmetic, against the FP64 oracle on the 32x16x16 standing wave
+    after 200 steps."""
     dims, tau, steps = (32, 16, 16), 0.6, 200
     F = wl.standing_wave(*dims, amp=1e-3)
-    ctx = gpu_run(L, dims, tau, F, steps, storage)
+    ctx = gpu_run(L, dims, tau, F, steps, storage, stochastic=sr)
     info = ctx.info()
     m_gpu = ctx.moments()
     ctx.free()
@@ -257,10 +265,10 @@ def test_shifted_storage_error_vs_fp64(L, orc, storage):
     m_ref = orc.moment_fields(f)
     errs = moment_errors(m_gpu, m_ref)
     drho = float(np.max(np.abs(m_gpu[0] - m_ref[0]))) / 1e-3
-    say("shifted", storage, "k_amp", info["shift_exp"], "per-field moment errors", ["%.2e" % e for e in errs],
-        "normwise %.2e" % rel_err(m_gpu, m_ref), "density error / amplitude %.2e" % drho)
+    say("shifted", storage, "SR" if sr else "RNE", "k_amp", info["shift_exp"], "per-field moment errors",
+        ["%.2e" % e for e in errs], "normwise %.2e" % rel_err(m_gpu, m_ref), "density error / amplitude %.2e" % drho)
     assert rel_err(m_gpu, m_ref) <= 1e-5
-    assert drho <= (2e-2 if storage == "f16s" else 3e-2)
+    assert drho <= {"f16s": 2e-2, "bf16s": 3e-2, "f32s": 1e-4, "f32": 1e-2}[storage]
 
 
 def _sampled_step_check(L, orc, dims, tau, F, storage, warm, nsample, tol, seed=0):
@@ -317,20 +325,20 @@ def test_sampled_full_size_pulse_512_f16s(L, orc):
     _sampled_step_check(L, orc, (512, 512, 512), 0.6, F, "f16s", 2, 1000, 1e-6)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16s", "bf16s"])
-def test_results_identical_across_launch_configurations(L, storage):
+@pytest.mark.parametrize("storage,sr", STORAGE_FORMS)
+def test_results_identical_across_launch_configurations(L, storage, sr):
     """Every step-kernel variant and tile mapping computes the same per-node
     arithmetic: the held state after a few steps must be bit-identical.
     A race in the streaming (reading a buffer that is being written) would
     show up as a dependence on the launch configuration."""
     dims, tau = (19, 11, 7), 0.57
-    say("launch invariance", storage)
+    say("launch invariance", storage, sr)
     F = wl.random_state(*dims, seed=41, amp_u=0.03, amp_rho=1e-3, amp_theta=1e-3)
     _, _, th = L.lattice()
     ref = None
     for v in range(L.num_variants()):
         for x in (0, 1):
-            ctx = L.init([(*dims, tau)], *F.absolute(th), storage=storage)
+            ctx = L.init([(*dims, tau)], *F.absolute(th), storage=storage, stochastic=sr)
             ctx.set_tuning(v, x)
             ctx.step(7)
             got = ctx.get_populations()
