@@ -2,14 +2,18 @@
 
 Workload: the precision-form acoustic pulse, 512^3 cells (2 nodes per cell,
 268,435,456 nodes), Gaussian density bump of amplitude 1e-3 and half width
-8 cells, u = 0, theta = theta0, tau_lb = 0.6. The headline storage is FP16
-holding f - w rho0 (FP32 arithmetic); FP32 storage of f is timed on the
-same grid for the speedup. A step is one launch of the fused kernel over
-all nodes; inputs are resident in HBM before timing starts.
+8 cells, u = 0, theta = theta0, tau_lb = 0.6. The headline form is FP16
+holding f - w rho0 with stochastic rounding (FP32 arithmetic); FP32 storage
+of f and the other forms are timed on the same grid. Each form is first
+autotuned (launch configuration), then a step is one launch of the fused
+kernel over all nodes, timed with HIP events on the context's stream; the
+inputs are resident in HBM before timing starts.
 
 Prints one JSON line. --gpus above 1 is refused: this build runs on one GPU.
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -20,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 ALGO_VALUES_PER_NODE = 82  # 41 loads + 41 stores per node update
+COUNTERS = os.path.join(ROOT, "profiles", "k_step_pulse512_hbm_counters.json")
 
 
 def parse():
@@ -28,14 +33,42 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=512, help="cells per edge of the periodic box")
-    ap.add_argument("--storages", default="f16s,f32", help="first one is the headline")
+    ap.add_argument("--forms", default="f16s+sr,f32,f16s,f32+sr,f32s,bf16s+sr",
+                    help="storage forms (a '+sr' suffix: stochastic rounding); the first is the headline")
     ap.add_argument("--tau", type=float, default=0.6)
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=128, help="cells per edge of the oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--copy-reference", type=float, default=0.0, metavar="GIB",
                     help="only time a plain device-to-device copy of GIB GiB (HBM counter reference)")
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1909_08406_amd", "csrc", "*"))):
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(form):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    try:
+        with open(COUNTERS) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256") != kernel_source_hash():
+        return None
+    rec = d.get("forms", {}).get(form)
+    if not rec:
+        return None
+    return {"fetch_bytes": rec["fetch_bytes"], "write_bytes": rec["write_bytes"],
+            "total_bytes": rec["fetch_bytes"] + rec["write_bytes"],
+            "scale": d.get("scale"), "source": os.path.relpath(COUNTERS, ROOT)}
 
 
 def copy_reference(torch, gib, reps=5):
@@ -56,11 +89,16 @@ def copy_reference(torch, gib, reps=5):
                       "gbs_read_plus_write": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
 
 
-def time_storage(lbm, torch, F, th, n, tau, storage, steps, warmup):
+def time_form(lbm, torch, F, th, n, tau, form, steps, warmup, autotune):
+    storage, _, sr = form.partition("+")
     stream = torch.cuda.Stream()
     t0 = time.time()
-    ctx = lbm.init([(n, n, n, tau)], *F.absolute(th), storage=storage, stream=stream)
+    ctx = lbm.init([(n, n, n, tau)], *F.absolute(th), storage=storage, stream=stream, stochastic=(sr == "sr"))
     init_s = time.time() - t0
+    tune = None
+    if autotune:
+        best, table = ctx.autotune(reps=3)
+        tune = {"variant": best[0], "xcd_remap": best[1], "block_threads": lbm.variant_desc(best[0])[0]}
     info = ctx.info()
     ctx.step(warmup)
     ctx.synchronize()
@@ -74,32 +112,28 @@ def time_storage(lbm, torch, F, th, n, tau, storage, steps, warmup):
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
     status = ctx.status()
-    tot = ctx.totals(check=False)[0]
     ctx.free()
     del ctx
     torch.cuda.empty_cache()
     nodes = info["nodes"]
-    eb = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[storage]
     ms_step = ms / steps
-    bytes_launch = ALGO_VALUES_PER_NODE * eb * nodes
+    bytes_launch = ALGO_VALUES_PER_NODE * lbm.ELEM_BYTES[storage] * nodes
     return {
-        "storage": storage,
+        "form": form,
         "ms_per_step": ms_step,
         "mlups": nodes * steps / (ms * 1e-3) / 1e6,
         "gbs": bytes_launch / (ms_step * 1e-3) / 1e9,
         "bytes_per_launch": bytes_launch,
         "nodes": nodes,
         "status": status,
-        "mass": tot[0],
-        "energy": tot[4],
         "init_s": init_s,
         "shift_exp": info["shift_exp"],
         "newton_iters": info["newton_iters"],
+        "tuning": tune,
     }
 
 
 def cpu_baseline(args):
-    import numpy as np  # noqa: F401
     import oracle
     from paper_1909_08406_amd import workloads as wl
 
@@ -116,9 +150,13 @@ def cpu_baseline(args):
         "unit": "MLUPS",
         "cores": oracle.threads(),
         "kind": "oracle",
-        "sample": "FP64 oracle, same pulse recipe (eps 1e-3, b 8) on %d^3 cells (%d nodes), %d steps, %.1f s"
-                  % (n, nodes, args.cpu_steps, dt),
+        "sample": "FP64 oracle (OpenMP over nodes), same pulse recipe (eps 1e-3, b 8, tau 0.6) on %d^3 cells "
+                  "(%d nodes), %d steps, %.1f s" % (n, nodes, args.cpu_steps, dt),
     }
+
+
+DTYPE = {"f16s": "f16-shifted storage, f32 compute", "bf16s": "bf16-shifted storage, f32 compute",
+         "f32": "f32", "f32s": "f32-shifted storage, f32 compute", "f64": "f64"}
 
 
 def main():
@@ -140,13 +178,13 @@ def main():
     n = args.n
     t0 = time.time()
     F = wl.gaussian_pulse(n, eps=1e-3, b=8.0)
-    gen_s = time.time() - t0
-    print("# fields %d^3 generated in %.1f s" % (n, gen_s), file=sys.stderr, flush=True)
+    print("# fields %d^3 generated in %.1f s" % (n, time.time() - t0), file=sys.stderr, flush=True)
     runs = []
-    for st in args.storages.split(","):
-        r = time_storage(lbm, torch, F, th, n, args.tau, st, args.steps, args.warmup)
-        print("# %s: %.3f ms/step, %.0f MLUPS, %.0f GB/s (init %.1f s)"
-              % (st, r["ms_per_step"], r["mlups"], r["gbs"], r["init_s"]), file=sys.stderr, flush=True)
+    for form in args.forms.split(","):
+        r = time_form(lbm, torch, F, th, n, args.tau, form, args.steps, args.warmup, not args.no_autotune)
+        print("# %s: %.3f ms/step, %.0f MLUPS, %.0f GB/s (init %.1f s, tuning %s)"
+              % (form, r["ms_per_step"], r["mlups"], r["gbs"], r["init_s"], r["tuning"]), file=sys.stderr,
+              flush=True)
         runs.append(r)
     del F
     head = runs[0]
@@ -154,6 +192,9 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args)
         print("# cpu baseline: %s" % cpu["sample"], file=sys.stderr, flush=True)
+    by = {r["form"]: {k: r[k] for k in ("mlups", "gbs", "ms_per_step", "status", "shift_exp", "newton_iters",
+                                        "tuning")} for r in runs}
+    traffic = measured_traffic(head["form"])
     out = {
         "metric": "MLUPS + achieved HBM GB/s, fused collide-stream, FP16-shifted vs FP32 storage",
         "value": head["mlups"],
@@ -165,24 +206,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f16s": "f16-shifted storage, f32 compute", "bf16s": "bf16-shifted storage, f32 compute",
-                  "f32": "f32", "f64": "f64"}[head["storage"]],
+        "dtype": DTYPE[head["form"].partition("+")[0]] + (", stochastic rounding" if "+sr" in head["form"] else ""),
         "data": "synthetic",
-        "config": {"workload": "periodic acoustic pulse %d^3 cells (%d nodes), eps 1e-3, b 8, tau 0.6, %s storage"
-                               % (n, head["nodes"], head["storage"]),
-                   "nodes": head["nodes"], "storage": head["storage"]},
+        "config": {"workload": "periodic acoustic pulse %d^3 cells (%d nodes), eps 1e-3, b 8, tau 0.6, %s"
+                               % (n, head["nodes"], head["form"]),
+                   "nodes": head["nodes"], "form": head["form"]},
         "achieved_gbs": head["gbs"],
-        "by_storage": {r["storage"]: {"mlups": r["mlups"], "gbs": r["gbs"], "ms_per_step": r["ms_per_step"],
-                                      "status": r["status"], "shift_exp": r["shift_exp"],
-                                      "newton_iters": r["newton_iters"]} for r in runs},
+        "by_form": by,
         "roofline": {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": head["gbs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_step<%s>" % head["storage"],
+                     "frac": head["gbs"] / HBM_PEAK_GBS,
+                     "traffic": traffic["total_bytes"] / (head["ms_per_step"] * 1e-3) / 1e9 if traffic else None,
+                     "traffic_bytes_per_launch": traffic,
+                     "kernel": "lbm::k_step (%s)" % head["form"],
                      "algorithmic_bytes_per_launch": head["bytes_per_launch"]},
         "cpu_baseline": cpu,
     }
-    if len(runs) > 1 and "f32" in out["by_storage"]:
-        out["speedup_vs_f32"] = head["mlups"] / out["by_storage"]["f32"]["mlups"]
+    if "f32" in by:
+        out["speedup_vs_f32"] = head["mlups"] / by["f32"]["mlups"]
     print(json.dumps(out), flush=True)
 
 
