@@ -147,7 +147,12 @@ int lbm_init(lbm_ctx **out, const lbm_box *boxes, int32_t nboxes, const lbm_opts
              const double *rho, const double *ux, const double *uy, const double *uz,
              const double *theta, void *stream, void *workspace, uint64_t workspace_bytes);
 
-/* n >= 0 fused collide-and-stream steps of every box (Sec. II), async. */
+/*
+ * n >= 0 fused collide-and-stream steps of every box (Sec. II), queued on
+ * the context stream without a host synchronisation. A step is one launch
+ * per box or one launch over all boxes, optionally replayed from captured
+ * graphs (see lbm_tuning); results do not depend on the choice.
+ */
 int lbm_step(lbm_ctx *ctx, int32_t n);
 
 /* Wait for all work queued on the context stream. */
@@ -210,11 +215,30 @@ int lbm_set_step_counter(lbm_ctx *ctx, uint32_t steps_done);
 /* Facts about the context (see lbm_info). */
 int lbm_get_info(lbm_ctx *ctx, lbm_info *info);
 
-/* Launch configuration of the step kernel. Every choice computes the same
- * per-node arithmetic, so results are identical across choices. */
+/* How a step is launched over the boxes of a context. */
+typedef enum {
+    LBM_SCHEDULE_PER_BOX = 0, /* one launch per box (default for one box) */
+    LBM_SCHEDULE_BATCHED = 1  /* one launch over every (box, tile) pair (default for several boxes) */
+} lbm_schedule;
+
+/* Largest graph_steps of lbm_tuning. */
+#define LBM_GRAPH_STEPS_MAX 1024
+
+/*
+ * Launch configuration of the step kernel. Every choice computes the same
+ * per-node arithmetic, so results are identical across choices.
+ * graph_steps: 0 launches every step from the host; an even value in
+ * [2, LBM_GRAPH_STEPS_MAX] makes lbm_step capture that many steps once as a
+ * hipGraph (per starting buffer) and replay it, leaving the remainder of n
+ * to eager launches. A graph holds no memset node; the stochastic-rounding
+ * step count of a replay is a device counter set by a one-thread kernel
+ * before each replay.
+ */
 typedef struct {
-    int32_t variant;    /* 0 .. lbm_num_variants()-1 (block size, cache hints) */
-    int32_t xcd_remap;  /* 1: consecutive tiles on one XCD (L2 domain); 0: dispatch order */
+    int32_t variant;     /* 0 .. lbm_num_variants()-1 (block size, cache hints) */
+    int32_t xcd_remap;   /* 1: consecutive tiles on one XCD (L2 domain); 0: dispatch order */
+    int32_t schedule;    /* lbm_schedule */
+    int32_t graph_steps; /* 0, or even in [2, LBM_GRAPH_STEPS_MAX] */
 } lbm_tuning;
 
 /* Number of step-kernel variants. No device needed. */
@@ -230,7 +254,7 @@ int lbm_get_tuning(lbm_ctx *ctx, lbm_tuning *t);
 
 /*
  * Time every (variant, xcd_remap) pair with `reps` steps each on the
- * context's own boxes and keep the fastest. The held state is unchanged
+ * context's own boxes (with its current schedule) and keep the fastest. The held state is unchanged
  * (each timed launch reads the current buffer and writes the other one).
  * ms (optional) receives 2*lbm_num_variants() mean step times, index
  * 2*variant + xcd_remap; best (optional) the choice. Synchronous.

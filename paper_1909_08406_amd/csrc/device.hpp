@@ -612,6 +612,8 @@ struct StepParams {
     uint32_t xcd_remap;    // 1: group consecutive tiles per XCD
     uint32_t step;         // step counter and seed of the stochastic rounding
     uint32_t seed;
+    uint32_t node0;        // index of the box's first node in the context (random-bit stream)
+    const uint32_t* step_base;  // null, or a device counter added to step (graph replays)
 };
 
 // Counter-based random bits for stochastic rounding: one hash per node and

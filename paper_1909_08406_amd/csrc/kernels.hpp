@@ -155,21 +155,18 @@ __device__ inline void st_hint(T* p, T v, int nt)
     }
 }
 
-template <class ST, int NEWTON, int BLK, int FL, bool SR>
-__global__ __launch_bounds__(BLK) void k_step(const typename ST::T* __restrict__ fin,
-                                              typename ST::T* __restrict__ fout, StepParams p)
+// The step of node n of one box: src and dst are the box's first q-block
+// in the current and the other population buffer.
+template <class ST, int NEWTON, int FL, bool SR>
+__device__ inline void step_node(const char* __restrict__ src, char* __restrict__ dst, const StepParams& p,
+                                 uint32_t n)
 {
     using R = typename ST::R;
     using T = typename ST::T;
-    const uint32_t blk = p.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
-    const uint32_t n = blk * BLK + threadIdx.x;
-    if (n >= p.g.N) return;
     const Coord c = decode(n, p.g);
     Nbr nb;
     make_nbr(p.g, c, nb, uint32_t(sizeof(T)));
     const uint64_t qbytes = uint64_t(p.g.N) * sizeof(T);
-    const char* src = reinterpret_cast<const char*>(fin);
-    char* dst = reinterpret_cast<char*>(fout);
 
     R x[Q];
     static_for<Q>([&](auto qc) {
@@ -191,7 +188,12 @@ __global__ __launch_bounds__(BLK) void k_step(const typename ST::T* __restrict__
     flag_bad<R>(p, rho, theta);
     const uint32_t nbytes = n * uint32_t(sizeof(T));
     uint32_t rs = 0, rw = 0;
-    if constexpr (SR) rs = hash32(n ^ hash32(p.step * 0x9e3779b9u + p.seed)) | 1u;
+    if constexpr (SR) {
+        // random bits per (node of the context, step): the step is the
+        // launch's own count plus, in graph replays, a device-held base
+        const uint32_t step = p.step + (p.step_base ? *p.step_base : 0u);
+        rs = hash32((p.node0 + n) ^ hash32(step * 0x9e3779b9u + p.seed)) | 1u;
+    }
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         T out;
@@ -206,6 +208,54 @@ __global__ __launch_bounds__(BLK) void k_step(const typename ST::T* __restrict__
         }
         st_hint(reinterpret_cast<T*>(dst + q * qbytes + uint64_t(nbytes)), out, FL & FL_NT_STORE);
     });
+}
+
+// One box per launch; fin/fout point at the box's first q-block.
+template <class ST, int NEWTON, int BLK, int FL, bool SR>
+__global__ __launch_bounds__(BLK) void k_step(const typename ST::T* __restrict__ fin,
+                                              typename ST::T* __restrict__ fout, StepParams p)
+{
+    const uint32_t blk = p.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t n = blk * BLK + threadIdx.x;
+    if (n >= p.g.N) return;
+    step_node<ST, NEWTON, FL, SR>(reinterpret_cast<const char*>(fin), reinterpret_cast<char*>(fout), p, n);
+}
+
+// ---------------------------------------------------------------------------
+// Batched step: every box of a context in one launch. The grid is the list
+// of (box, tile) pairs, box after box, each box cut into tiles of BLK nodes
+// (its last tile ragged); a block reads its pair from `tiles`, the box's
+// parameters from `boxes` (both uniform across the block, so they sit in
+// scalar registers) and runs the same per-node step as k_step.
+// ---------------------------------------------------------------------------
+struct BatchBox {
+    StepParams p;     // geometry, omega, storage scales and node0 of the box
+    uint64_t offset;  // element offset of the box in a population buffer
+};
+
+template <class ST, int NEWTON, int BLK, int FL, bool SR>
+__global__ __launch_bounds__(BLK) void k_step_batch(const typename ST::T* __restrict__ fin,
+                                                    typename ST::T* __restrict__ fout,
+                                                    const BatchBox* __restrict__ boxes,
+                                                    const uint2* __restrict__ tiles, uint32_t xcd_remap,
+                                                    uint32_t step, const uint32_t* __restrict__ step_base)
+{
+    const uint32_t t = xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint2 bt = tiles[t];  // (box, tile within the box)
+    const BatchBox& B = boxes[bt.x];
+    const uint32_t n = bt.y * BLK + threadIdx.x;
+    if (n >= B.p.g.N) return;
+    StepParams p = B.p;
+    p.step = step;
+    p.step_base = step_base;
+    step_node<ST, NEWTON, FL, SR>(reinterpret_cast<const char*>(fin + B.offset), reinterpret_cast<char*>(fout + B.offset),
+                                  p, n);
+}
+
+// Device-held step counter read by graph replays (one vector store).
+__global__ void k_set_counter(uint32_t* __restrict__ ctr, uint32_t v)
+{
+    if (threadIdx.x == 0) ctr[0] = v;
 }
 
 // ---------------------------------------------------------------------------

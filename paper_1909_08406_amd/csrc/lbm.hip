@@ -45,14 +45,28 @@ struct BoxDev {
     double omega;
     uint64_t offset;  // element offset of this box in a population buffer
     uint64_t nodes;
+    uint64_t node0;   // index of the box's first node in the context
 };
+
+// Block sizes of the step-kernel variants; the batched launch keeps one
+// (box, tile) list per block size.
+constexpr int NBLK = 4;
+constexpr int BLK_SIZES[NBLK] = {128, 256, 512, 1024};
+constexpr int blk_index(int blk) { return blk == 128 ? 0 : blk == 256 ? 1 : blk == 512 ? 2 : 3; }
 
 struct Layout {
     uint64_t elems = 0;      // elements per population buffer
     uint64_t buf_bytes = 0;  // bytes per population buffer (aligned)
     uint64_t flag_off = 0, partial_off = 0, staging_off = 0, staging_bytes = 0, total = 0;
+    uint64_t table_off = 0;          // BatchBox per box
+    uint64_t tiles_off[NBLK] = {};   // (box, tile) pairs per block size
+    uint64_t ntiles[NBLK] = {};
     uint64_t max_nodes = 0;
 };
+
+// In the flag area: the non-finite flag at byte 0, the device step counter
+// of graph replays at byte COUNTER_OFF.
+constexpr uint64_t COUNTER_OFF = 64;
 
 int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
 {
@@ -67,6 +81,7 @@ int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
         return LBM_E_ARG;
     if (!(opts->rho0 >= 0.0) || !std::isfinite(opts->rho0)) return LBM_E_ARG;
     if (opts->shift_exp != LBM_SHIFT_AUTO && (opts->shift_exp < -60 || opts->shift_exp > 60)) return LBM_E_ARG;
+    uint64_t tiles = 0;
     for (int b = 0; b < nboxes; ++b) {
         const lbm_box& x = boxes[b];
         if (x.nx < 1 || x.ny < 1 || x.nz < 1 || x.reserved != 0) return LBM_E_ARG;
@@ -76,7 +91,10 @@ int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
         if (!std::isfinite(x.tau)) return LBM_E_ARG;
         if (opts->tau_conv == LBM_TAU_LB && !(x.tau > 0.5)) return LBM_E_ARG;
         if (opts->tau_conv == LBM_TAU_PAPER && !(x.tau > 0.0)) return LBM_E_ARG;
+        tiles += (nodes + 127) / 128;
     }
+    // the batched launch has one block per (box, 128-node tile)
+    if (tiles >= (1ull << 31)) return LBM_E_ARG;
     return LBM_OK;
 }
 
@@ -91,7 +109,17 @@ Layout plan(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
     }
     L.buf_bytes = align_up(L.elems * eb);
     L.flag_off = 2 * L.buf_bytes;
-    L.partial_off = L.flag_off + ALIGN;
+    L.table_off = L.flag_off + ALIGN;
+    uint64_t off = L.table_off + align_up(uint64_t(nboxes) * sizeof(BatchBox));
+    for (int i = 0; i < NBLK; ++i) {
+        for (int b = 0; b < nboxes; ++b) {
+            const uint64_t nodes = 2ull * uint64_t(boxes[b].nx) * boxes[b].ny * boxes[b].nz;
+            L.ntiles[i] += (nodes + BLK_SIZES[i] - 1) / BLK_SIZES[i];
+        }
+        L.tiles_off[i] = off;
+        off += align_up(L.ntiles[i] * sizeof(uint2));
+    }
+    L.partial_off = off;
     // partial sums: up to TOTAL_BLOCKS blocks of 2*PROJ_FIELDS doubles, then the result
     L.staging_off = L.partial_off + align_up(uint64_t(TOTAL_BLOCKS + 1) * 2 * PROJ_FIELDS * sizeof(double));
     // staging holds chunks of FP64 node fields (5 per node) or populations
@@ -123,6 +151,17 @@ struct lbm_ctx {
     double rho_ref_storage = 0.0;  // rho0 for shifted storage, else 0
     bool stochastic = false;       // stochastic rounding of the stored values
     uint32_t steps_done = 0;       // counter feeding the stochastic rounding
+    int schedule = LBM_SCHEDULE_PER_BOX;
+    int graph_steps = 0;           // 0: eager launches; else steps per captured graph
+    BatchBox* table = nullptr;     // device: per-box parameters of the batched launch
+    uint2* tiles[NBLK] = {};       // device: (box, tile) lists per block size
+    uint32_t* step_ctr = nullptr;  // device: step base read by graph replays
+    struct Graph {
+        int cur;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;     // captured step sequences for the current tuning
+    hipStream_t capture = nullptr; // private stream the graphs are captured on
 
     char* buf(int i) const { return mem + uint64_t(i) * L.buf_bytes; }
     StepParams params(const BoxDev& b) const
@@ -130,6 +169,7 @@ struct lbm_ctx {
         StepParams p = base;
         p.g = b.g;
         p.omega = b.omega;
+        p.node0 = uint32_t(b.node0);
         p.step = steps_done;
         // the kernel's reference weights are the FP32-rounded ones
         for (int s = 0; s < 6; ++s)
@@ -171,66 +211,147 @@ constexpr VariantDesc VARIANTS[] = {
 };
 constexpr int NVARIANTS = int(sizeof(VARIANTS) / sizeof(VARIANTS[0]));
 
-template <class ST, int NEWTON, int BLK, int FL, bool SR>
-void launch_k(const BoxDev& b, hipStream_t st, const typename ST::T* in, typename ST::T* out, const StepParams& p)
+// Calls f(integral_constant<BLK>, integral_constant<FL>) for variant v.
+template <class F>
+int with_variant(int v, F&& f)
 {
-    hipLaunchKernelGGL((k_step<ST, NEWTON, BLK, FL, SR>), dim3(uint32_t((b.nodes + BLK - 1) / BLK)), dim3(BLK), 0,
-                       st, in, out, p);
-}
-
-template <class ST, int NEWTON, bool SR>
-int launch_variant(int v, const BoxDev& b, hipStream_t st, const typename ST::T* in, typename ST::T* out,
-                   const StepParams& p)
-{
+    using std::integral_constant;
     switch (v) {
-        case 0: launch_k<ST, NEWTON, 256, 0, SR>(b, st, in, out, p); break;
-        case 1: launch_k<ST, NEWTON, 256, FL_NT_LOAD | FL_NT_STORE, SR>(b, st, in, out, p); break;
-        case 2: launch_k<ST, NEWTON, 512, 0, SR>(b, st, in, out, p); break;
-        case 3: launch_k<ST, NEWTON, 128, 0, SR>(b, st, in, out, p); break;
-        case 4: launch_k<ST, NEWTON, 256, FL_NT_STORE, SR>(b, st, in, out, p); break;
-        case 5: launch_k<ST, NEWTON, 1024, 0, SR>(b, st, in, out, p); break;
+        case 0: f(integral_constant<int, 256>{}, integral_constant<int, 0>{}); break;
+        case 1: f(integral_constant<int, 256>{}, integral_constant<int, FL_NT_LOAD | FL_NT_STORE>{}); break;
+        case 2: f(integral_constant<int, 512>{}, integral_constant<int, 0>{}); break;
+        case 3: f(integral_constant<int, 128>{}, integral_constant<int, 0>{}); break;
+        case 4: f(integral_constant<int, 256>{}, integral_constant<int, FL_NT_STORE>{}); break;
+        case 5: f(integral_constant<int, 1024>{}, integral_constant<int, 0>{}); break;
         default: return LBM_E_ARG;
     }
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
 }
 
-template <class ST, int NEWTON>
-int launch_newton(lbm_ctx* ctx, const BoxDev& b, const typename ST::T* in, typename ST::T* out,
-                  const StepParams& p)
+template <class F>
+int with_newton(int n, F&& f)
 {
-    // stochastic rounding exists for the FP32-arithmetic forms whose
-    // rounding is coarse: FP32 of f, FP16 and BF16 of the shift
-    constexpr bool has_sr = std::is_same<ST, StoreF32>::value || std::is_same<ST, StoreF16S>::value ||
-                            std::is_same<ST, StoreBF16S>::value;
-    if constexpr (has_sr) {
-        if (ctx->stochastic) return launch_variant<ST, NEWTON, true>(ctx->variant, b, ctx->stream, in, out, p);
-    }
-    return launch_variant<ST, NEWTON, false>(ctx->variant, b, ctx->stream, in, out, p);
-}
-
-template <class ST>
-int launch_step_typed(lbm_ctx* ctx, const BoxDev& b, const typename ST::T* in, typename ST::T* out)
-{
-    const StepParams p = ctx->params(b);
-    switch (ctx->newton) {
-        case 1: return launch_newton<ST, 1>(ctx, b, in, out, p);
-        case 2: return launch_newton<ST, 2>(ctx, b, in, out, p);
-        case 3: return launch_newton<ST, 3>(ctx, b, in, out, p);
-        case 4: return launch_newton<ST, 4>(ctx, b, in, out, p);
+    using std::integral_constant;
+    switch (n) {
+        case 1: return f(integral_constant<int, 1>{});
+        case 2: return f(integral_constant<int, 2>{});
+        case 3: return f(integral_constant<int, 3>{});
+        case 4: return f(integral_constant<int, 4>{});
         default: return LBM_E_ARG;
     }
 }
 
-// One step of box b from buffer `from` into the other buffer.
-int launch_step(lbm_ctx* ctx, const BoxDev& b, int from)
+// Enqueue one step of every box from buffer `from` into the other buffer on
+// stream s. The stochastic-rounding step is `step`, plus *step_base when
+// step_base is not null (graph replays).
+int enqueue_step(lbm_ctx* ctx, int from, uint32_t step, const uint32_t* step_base, hipStream_t s)
 {
     return dispatch_storage(ctx->storage, [&](auto st) {
         using ST = decltype(st);
         using T = typename ST::T;
-        const T* in = reinterpret_cast<const T*>(ctx->buf(from)) + b.offset;
-        T* out = reinterpret_cast<T*>(ctx->buf(1 - from)) + b.offset;
-        return launch_step_typed<ST>(ctx, b, in, out);
+        const T* in = reinterpret_cast<const T*>(ctx->buf(from));
+        T* out = reinterpret_cast<T*>(ctx->buf(1 - from));
+        // stochastic rounding exists for the FP32-arithmetic forms whose
+        // rounding is coarse: FP32 of f, FP16 and BF16 of the shift
+        constexpr bool has_sr = std::is_same<ST, StoreF32>::value || std::is_same<ST, StoreF16S>::value ||
+                                std::is_same<ST, StoreBF16S>::value;
+        return with_newton(ctx->newton, [&](auto nw) {
+            constexpr int NEWTON = decltype(nw)::value;
+            auto go = [&](auto sr) {
+                constexpr bool SR = decltype(sr)::value;
+                return with_variant(ctx->variant, [&](auto blk, auto fl) {
+                    constexpr int BLK = decltype(blk)::value;
+                    constexpr int FL = decltype(fl)::value;
+                    if (ctx->schedule == LBM_SCHEDULE_BATCHED) {
+                        const int i = blk_index(BLK);
+                        hipLaunchKernelGGL((k_step_batch<ST, NEWTON, BLK, FL, SR>), dim3(uint32_t(ctx->L.ntiles[i])),
+                                           dim3(BLK), 0, s, in, out, ctx->table, ctx->tiles[i], ctx->base.xcd_remap,
+                                           step, step_base);
+                    } else {
+                        for (const BoxDev& b : ctx->boxes) {
+                            StepParams p = ctx->params(b);
+                            p.step = step;
+                            p.step_base = step_base;
+                            hipLaunchKernelGGL((k_step<ST, NEWTON, BLK, FL, SR>),
+                                               dim3(uint32_t((b.nodes + BLK - 1) / BLK)), dim3(BLK), 0, s,
+                                               in + b.offset, out + b.offset, p);
+                        }
+                    }
+                });
+            };
+            if constexpr (has_sr) {
+                if (ctx->stochastic) return go(std::true_type{});
+            }
+            return go(std::false_type{});
+        });
     });
+}
+
+// Device tables of the batched launch: per-box parameters and, per block
+// size, the (box, tile) list. Called once the storage scales are final.
+int upload_tables(lbm_ctx* ctx)
+{
+    std::vector<BatchBox> tab(ctx->boxes.size());
+    for (size_t b = 0; b < ctx->boxes.size(); ++b) {
+        tab[b].p = ctx->params(ctx->boxes[b]);
+        tab[b].p.step = 0;
+        tab[b].p.step_base = nullptr;
+        tab[b].offset = ctx->boxes[b].offset;
+    }
+    HIPCHK(hipMemcpyAsync(ctx->table, tab.data(), tab.size() * sizeof(BatchBox), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < NBLK; ++i) {
+        std::vector<uint2> t;
+        t.reserve(ctx->L.ntiles[i]);
+        for (size_t b = 0; b < ctx->boxes.size(); ++b) {
+            const uint64_t nt = (ctx->boxes[b].nodes + BLK_SIZES[i] - 1) / BLK_SIZES[i];
+            for (uint64_t k = 0; k < nt; ++k) t.push_back(make_uint2(uint32_t(b), uint32_t(k)));
+        }
+        if (t.size() != ctx->L.ntiles[i]) return LBM_E_ARG;
+        HIPCHK(hipMemcpyAsync(ctx->tiles[i], t.data(), t.size() * sizeof(uint2), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return LBM_OK;
+}
+
+void drop_graphs(lbm_ctx* ctx)
+{
+    for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    ctx->graphs.clear();
+}
+
+// The executable graph of graph_steps steps starting from buffer ctx->cur
+// (graph_steps is even, so a replay ends on the same buffer), captured on
+// the private stream the first time it is asked for.
+int graph_for(lbm_ctx* ctx, hipGraphExec_t* out)
+{
+    for (auto& g : ctx->graphs)
+        if (g.cur == ctx->cur) {
+            *out = g.exec;
+            return LBM_OK;
+        }
+    if (!ctx->capture) HIPCHK(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+    int rc = LBM_OK;
+    int from = ctx->cur;
+    for (int i = 0; i < ctx->graph_steps && rc == LBM_OK; ++i) {
+        rc = enqueue_step(ctx, from, uint32_t(i), ctx->step_ctr, ctx->capture);
+        from ^= 1;
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->capture, &graph);
+    if (rc != LBM_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return rc != LBM_OK ? rc : LBM_E_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) return LBM_E_HIP;
+    ctx->graphs.push_back({ctx->cur, exec});
+    *out = exec;
+    return LBM_OK;
 }
 
 // Copy nodal FP64 fields of box b chunk by chunk and run the init kernel.
@@ -335,13 +456,15 @@ int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts
     const bool shifted = opts->storage == LBM_F16_SHIFT || opts->storage == LBM_BF16_SHIFT ||
                          opts->storage == LBM_F32_SHIFT;
 
-    uint64_t off = 0;
+    uint64_t off = 0, node0 = 0;
     for (int b = 0; b < nboxes; ++b) {
         BoxDev d;
         d.g = make_geom(uint32_t(boxes[b].nx), uint32_t(boxes[b].ny), uint32_t(boxes[b].nz));
         d.nodes = d.g.N;
         d.offset = off;
+        d.node0 = node0;
         off += uint64_t(Q) * d.nodes;
+        node0 += d.nodes;
         d.omega = opts->tau_conv == LBM_TAU_LB ? 1.0 / boxes[b].tau : 2.0 / (2.0 * boxes[b].tau + 1.0);
         ctx->boxes.push_back(d);
     }
@@ -381,6 +504,10 @@ int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts
         ctx->own_mem = true;
     }
     ctx->flag = reinterpret_cast<uint32_t*>(ctx->mem + ctx->L.flag_off);
+    ctx->step_ctr = reinterpret_cast<uint32_t*>(ctx->mem + ctx->L.flag_off + COUNTER_OFF);
+    ctx->table = reinterpret_cast<BatchBox*>(ctx->mem + ctx->L.table_off);
+    for (int i = 0; i < NBLK; ++i) ctx->tiles[i] = reinterpret_cast<uint2*>(ctx->mem + ctx->L.tiles_off[i]);
+    ctx->schedule = nboxes > 1 ? LBM_SCHEDULE_BATCHED : LBM_SCHEDULE_PER_BOX;
     ctx->partials = reinterpret_cast<double*>(ctx->mem + ctx->L.partial_off);
     ctx->staging = ctx->mem + ctx->L.staging_off;
 
@@ -431,6 +558,8 @@ int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts
     uint32_t flag = 0;
     if (hipMemcpy(&flag, ctx->flag, sizeof(flag), hipMemcpyDeviceToHost) != hipSuccess) return fail(LBM_E_HIP);
     if (flag) return fail(LBM_E_DOMAIN);
+    rc = upload_tables(ctx);
+    if (rc) return fail(rc);
     *out = ctx;
     return LBM_OK;
 }
@@ -438,11 +567,21 @@ int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts
 int lbm_step(lbm_ctx* ctx, int32_t n)
 {
     if (!ctx || n < 0) return LBM_E_ARG;
+    // whole graphs first (each ends on the buffer it started from), then
+    // the remaining steps as eager launches
+    while (ctx->graph_steps > 0 && n >= ctx->graph_steps) {
+        hipGraphExec_t exec = nullptr;
+        int rc = graph_for(ctx, &exec);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(64), 0, ctx->stream, ctx->step_ctr, ctx->steps_done);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipGraphLaunch(exec, ctx->stream));
+        ctx->steps_done += uint32_t(ctx->graph_steps);
+        n -= ctx->graph_steps;
+    }
     for (int32_t i = 0; i < n; ++i) {
-        for (const BoxDev& b : ctx->boxes) {
-            int rc = launch_step(ctx, b, ctx->cur);
-            if (rc) return rc;
-        }
+        int rc = enqueue_step(ctx, ctx->cur, ctx->steps_done, nullptr, ctx->stream);
+        if (rc) return rc;
         ctx->cur ^= 1;
         ++ctx->steps_done;
     }
@@ -690,10 +829,20 @@ int lbm_variant_desc(int32_t variant, int32_t* block_threads, uint32_t* flags)
 
 int lbm_set_tuning(lbm_ctx* ctx, const lbm_tuning* t)
 {
-    if (!ctx || !t || t->variant < 0 || t->variant >= NVARIANTS || (t->xcd_remap != 0 && t->xcd_remap != 1))
+    if (!ctx || !t || t->variant < 0 || t->variant >= NVARIANTS || (t->xcd_remap != 0 && t->xcd_remap != 1) ||
+        (t->schedule != LBM_SCHEDULE_PER_BOX && t->schedule != LBM_SCHEDULE_BATCHED) || t->graph_steps < 0 ||
+        t->graph_steps > LBM_GRAPH_STEPS_MAX || (t->graph_steps % 2) != 0)
         return LBM_E_ARG;
+    if (t->variant != ctx->variant || uint32_t(t->xcd_remap) != ctx->base.xcd_remap ||
+        t->schedule != ctx->schedule || t->graph_steps != ctx->graph_steps) {
+        // captured graphs hold the old launch configuration
+        if (!ctx->graphs.empty()) HIPCHK(hipStreamSynchronize(ctx->stream));
+        drop_graphs(ctx);
+    }
     ctx->variant = t->variant;
     ctx->base.xcd_remap = uint32_t(t->xcd_remap);
+    ctx->schedule = t->schedule;
+    ctx->graph_steps = t->graph_steps;
     return LBM_OK;
 }
 
@@ -702,6 +851,8 @@ int lbm_get_tuning(lbm_ctx* ctx, lbm_tuning* t)
     if (!ctx || !t) return LBM_E_ARG;
     t->variant = ctx->variant;
     t->xcd_remap = int32_t(ctx->base.xcd_remap);
+    t->schedule = ctx->schedule;
+    t->graph_steps = ctx->graph_steps;
     return LBM_OK;
 }
 
@@ -718,7 +869,7 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, float* ms, lbm_tuning* best)
     const uint32_t saved_x = ctx->base.xcd_remap;
     int rc = LBM_OK;
     float best_ms = 0.f;
-    lbm_tuning bt{saved_v, int32_t(saved_x)};
+    lbm_tuning bt{saved_v, int32_t(saved_x), ctx->schedule, ctx->graph_steps};
     for (int v = 0; v < NVARIANTS && rc == LBM_OK; ++v) {
         for (int x = 0; x < 2 && rc == LBM_OK; ++x) {
             ctx->variant = v;
@@ -727,8 +878,7 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, float* ms, lbm_tuning* best)
             // the held state is left unchanged
             for (int r = -1; r < reps && rc == LBM_OK; ++r) {
                 if (r == 0 && hipEventRecord(e0, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
-                for (const BoxDev& b : ctx->boxes)
-                    if (rc == LBM_OK) rc = launch_step(ctx, b, ctx->cur);
+                if (rc == LBM_OK) rc = enqueue_step(ctx, ctx->cur, ctx->steps_done, nullptr, ctx->stream);
             }
             if (rc == LBM_OK && hipEventRecord(e1, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
             if (rc == LBM_OK && hipEventSynchronize(e1) != hipSuccess) rc = LBM_E_HIP;
@@ -750,6 +900,7 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, float* ms, lbm_tuning* best)
         ctx->base.xcd_remap = saved_x;
         return rc;
     }
+    if (bt.variant != saved_v || uint32_t(bt.xcd_remap) != saved_x) drop_graphs(ctx);  // stream is idle here
     ctx->variant = bt.variant;
     ctx->base.xcd_remap = uint32_t(bt.xcd_remap);
     if (best) *best = bt;
@@ -762,6 +913,8 @@ void lbm_free(lbm_ctx* ctx)
 {
     if (!ctx) return;
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    drop_graphs(ctx);
+    if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     if (ctx->own_mem && ctx->mem) (void)hipFree(ctx->mem);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;

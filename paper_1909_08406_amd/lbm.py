@@ -49,7 +49,13 @@ class Info(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("variant", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+    _fields_ = [("variant", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("graph_steps", ctypes.c_int32)]
+
+
+# lbm_schedule: one launch per box, or one launch over every (box, tile)
+SCHEDULES = {"per_box": 0, "batched": 1}
+GRAPH_STEPS_MAX = 1024
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -231,14 +237,35 @@ class Context:
     def stream(self):
         return lib().lbm_stream(self.handle)
 
-    def set_tuning(self, variant, xcd_remap):
-        t = Tuning(int(variant), int(xcd_remap))
+    def set_tuning(self, variant=None, xcd_remap=None, schedule=None, graph_steps=None):
+        """Change any of the launch settings (the others are kept). schedule:
+        "per_box" or "batched"; graph_steps: 0 or an even count of steps per
+        captured graph."""
+        t = Tuning()
+        _check(lib().lbm_get_tuning(self.handle, ctypes.byref(t)), "lbm_get_tuning")
+        if variant is not None:
+            t.variant = int(variant)
+        if xcd_remap is not None:
+            t.xcd_remap = int(xcd_remap)
+        if schedule is not None:
+            t.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+        if graph_steps is not None:
+            t.graph_steps = int(graph_steps)
         _check(lib().lbm_set_tuning(self.handle, ctypes.byref(t)), "lbm_set_tuning")
 
     def get_tuning(self):
+        """(variant, xcd_remap) of the step kernel."""
         t = Tuning()
         _check(lib().lbm_get_tuning(self.handle, ctypes.byref(t)), "lbm_get_tuning")
         return t.variant, t.xcd_remap
+
+    def tuning(self):
+        """Every launch setting as a dict."""
+        t = Tuning()
+        _check(lib().lbm_get_tuning(self.handle, ctypes.byref(t)), "lbm_get_tuning")
+        names = {v: k for k, v in SCHEDULES.items()}
+        return {"variant": t.variant, "xcd_remap": t.xcd_remap, "schedule": names.get(t.schedule, t.schedule),
+                "graph_steps": t.graph_steps}
 
     def autotune(self, reps=3):
         """Times every launch configuration, keeps the fastest; returns
