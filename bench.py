@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=128, help="cells per edge of the oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-box batch measurement")
+    ap.add_argument("--batch-forms", default="f16s+sr,f32")
+    ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--copy-reference", type=float, default=0.0, metavar="GIB",
                     help="only time a plain device-to-device copy of GIB GiB (HBM counter reference)")
     return ap.parse_args()
@@ -133,6 +136,43 @@ def time_form(lbm, torch, F, th, n, tau, form, steps, warmup, autotune):
     }
 
 
+def time_batch(lbm, torch, form, steps, warmup, autotune):
+    """The 256-box batch of uneven periodic standing-wave boxes (edges from
+    {16, 24, 32, 48, 64, 96}, seed 0) in one context: one launch per step
+    over every (box, tile), eager and replayed from captured graphs."""
+    from paper_1909_08406_amd import workloads as wl
+
+    storage, _, sr = form.partition("+")
+    specs = wl.batch_specs()
+    cat = wl.concat([wl.batch_fields(b) for b in specs])
+    _, _, th = lbm.lattice()
+    stream = torch.cuda.Stream()
+    ctx = lbm.init([(b.nx, b.ny, b.nz, b.tau) for b in specs], cat[0], cat[1], cat[2], cat[3], cat[4] * th,
+                   storage=storage, stream=stream, stochastic=(sr == "sr"))
+    del cat
+    if autotune:
+        ctx.autotune(reps=3)
+    nodes = ctx.info()["nodes"]
+    out = {"nodes": nodes, "tuning": ctx.tuning()}
+    for mode, g in (("eager", 0), ("graph", 10)):
+        ctx.set_tuning(graph_steps=g)
+        ctx.step(max(warmup, g))
+        ctx.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        ctx.step(steps)
+        end.record(stream)
+        end.synchronize()
+        ms = start.elapsed_time(end) / steps
+        bytes_launch = ALGO_VALUES_PER_NODE * lbm.ELEM_BYTES[storage] * nodes
+        out[mode] = {"ms_per_step": ms, "mlups": nodes / (ms * 1e-3) / 1e6, "gbs": bytes_launch / (ms * 1e-3) / 1e9}
+    out["status"] = ctx.status()
+    ctx.free()
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(args):
     import oracle
     from paper_1909_08406_amd import workloads as wl
@@ -187,6 +227,19 @@ def main():
               flush=True)
         runs.append(r)
     del F
+    batch = None
+    if not args.no_batch:
+        batch = {"workload": "256 periodic standing-wave boxes, edges from {16,24,32,48,64,96}, k 1..4, "
+                             "tau U[0.51,1), amplitude 10^U[-4,-2], seed 0; one launch per step over all boxes",
+                 "forms": {}}
+        for form in args.batch_forms.split(","):
+            r = time_batch(lbm, torch, form, args.batch_steps, args.warmup, not args.no_autotune)
+            batch["nodes"] = r.pop("nodes")
+            batch["forms"][form] = r
+            print("# batch %s: eager %.3f ms/step %.0f MLUPS %.0f GB/s; graph %.3f ms/step %.0f MLUPS %.0f GB/s (%s)"
+                  % (form, r["eager"]["ms_per_step"], r["eager"]["mlups"], r["eager"]["gbs"],
+                     r["graph"]["ms_per_step"], r["graph"]["mlups"], r["graph"]["gbs"], r["tuning"]),
+                  file=sys.stderr, flush=True)
     head = runs[0]
     cpu = None
     if not args.no_cpu_baseline:
@@ -220,6 +273,7 @@ def main():
                      "kernel": "lbm::k_step (%s)" % head["form"],
                      "algorithmic_bytes_per_launch": head["bytes_per_launch"]},
         "cpu_baseline": cpu,
+        "batch": batch,
     }
     if "f32" in by:
         out["speedup_vs_f32"] = head["mlups"] / by["f32"]["mlups"]

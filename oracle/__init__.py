@@ -83,6 +83,15 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def _pops(f, n=None, copy=False):
+    """Populations as a C-contiguous FP64 (41, N) array; N checked when
+    given (the C side trusts the sizes it is passed)."""
+    a = np.array(f, dtype=np.float64, copy=True, order="C") if copy else _f64(f)
+    if a.size % NQ or (n is not None and a.size != NQ * n):
+        raise ValueError("populations of size %d do not hold 41 x %s values" % (a.size, n))
+    return a.reshape(NQ, a.size // NQ)
+
+
 def lattice():
     """(c[41,3], w[41], theta0) in the canonical velocity order."""
     lib = _load()
@@ -188,7 +197,7 @@ def init(nx, ny, nz, rho, ux, uy, uz, theta):
 
 
 def collide_field(nx, ny, nz, omega, f):
-    f = _f64(f)
+    f = _pops(f, 2 * nx * ny * nz)
     out = np.zeros_like(f)
     rc = _load().orc_collide_field(nx, ny, nz, float(omega), _d(f), _d(out))
     if rc != 0:
@@ -198,7 +207,7 @@ def collide_field(nx, ny, nz, omega, f):
 
 def run(nx, ny, nz, omega, f, nsteps):
     """Advance populations f [41, N] by nsteps collide+push steps (in place copy returned)."""
-    f = np.array(f, dtype=np.float64, copy=True, order="C")
+    f = _pops(f, 2 * nx * ny * nz, copy=True)
     tmp = np.empty_like(f)
     rc = _load().orc_run(nx, ny, nz, float(omega), _d(f), _d(tmp), int(nsteps))
     if rc != 0:
@@ -208,7 +217,7 @@ def run(nx, ny, nz, omega, f, nsteps):
 
 def moment_fields(f):
     """(rho, jx, jy, jz, E) per node from populations [41, N]."""
-    f = _f64(f)
+    f = _pops(f)
     n = f.shape[-1]
     m = np.zeros((5, n))
     _load().orc_moment_fields(n, _d(f), *[_d(m[k]) for k in range(5)])
@@ -216,7 +225,7 @@ def moment_fields(f):
 
 
 def totals(f):
-    f = _f64(f)
+    f = _pops(f)
     out = np.zeros(5)
     _load().orc_totals(f.shape[-1], _d(f), _d(out))
     return out

@@ -59,6 +59,63 @@ def fourier_mode(field, nx, ny, nz, kvec):
     return np.sum(f * ph) / f.size
 
 
+def linear_step_matrix(c, w, kvec, omega):
+    """One step of the lattice BGK scheme, linearised about the rest state
+    f_i = w_i (rho 1, u 0, theta theta0), acting on the amplitudes a_i of a
+    Fourier mode a_i exp(i k.x) over the bcc node positions (Sec. II: relax
+    with rate omega toward the equilibrium of Sec. V, then move along c_i).
+
+    The equilibrium has the exponential form w_i exp(lambda.phi_i) with
+    phi = (1, c, c^2) and lambda = 0 at the rest state, so its derivative is
+    d f_eq = W Phi (Phi^T W Phi)^{-1} Phi^T d f: the w-weighted projection of
+    d f onto span(1, c, c^2) that keeps the five conserved moments. Moving
+    along c_i brings to x what was at x - c_i (a node of the bcc lattice for
+    every c_i, half-integer ones included), i.e. multiplies a_i by
+    exp(-i k.c_i). Returns the 41 x 41 complex matrix S (I + omega (J - I))."""
+    c = np.asarray(c, dtype=float).reshape(-1, 3)
+    w = np.asarray(w, dtype=float)
+    q = w.size
+    phi = np.column_stack([np.ones(q), c, np.sum(c * c, axis=1)])
+    gram = phi.T @ (w[:, None] * phi)
+    J = (w[:, None] * phi) @ np.linalg.solve(gram, phi.T)
+    C = (1.0 - omega) * np.eye(q) + omega * J
+    S = np.exp(-1j * (c @ np.asarray(kvec, dtype=float)))
+    return S[:, None] * C
+
+
+def linear_moment_series(c, w, kvec, omega, a0, steps):
+    """Amplitudes of (rho, jx, jy, jz, E) of the mode after t = 0..steps
+    steps of the linearised scheme from population amplitudes a0:
+    array (steps + 1, 5); E = sum_i f_i c_i^2 / 2."""
+    c = np.asarray(c, dtype=float).reshape(-1, 3)
+    M = linear_step_matrix(c, w, kvec, omega)
+    P = np.vstack([np.ones(len(c)), c.T, 0.5 * np.sum(c * c, axis=1)])
+    a = np.asarray(a0, dtype=complex)
+    out = np.empty((steps + 1, 5), dtype=complex)
+    for t in range(steps + 1):
+        out[t] = P @ a
+        a = M @ a
+    return out
+
+
+def linear_modes(c, w, kvec, omega):
+    """Hydrodynamic eigenvalues of the linearised step for wavevector k, as
+    rates per step: (acoustic log-eigenvalue with Im > 0, entropy rate).
+    The acoustic pair and the entropy mode are the eigenvalues closest to
+    exp(+-i c_s |k|) and 1 among those of modulus near 1."""
+    ev = np.linalg.eigvals(linear_step_matrix(c, w, kvec, omega))
+    lg = np.log(ev.astype(complex))
+    # slow modes: the five with the smallest decay (two acoustic, one
+    # entropy, two shear); acoustic ones have the largest |Im|
+    slow = lg[np.argsort(-lg.real)[:5]]
+    ac = slow[np.argmax(slow.imag)]
+    rest = [z for z in slow if abs(z.imag) < 0.5 * ac.imag]
+    # entropy vs shear: for Prandtl 1 the shear rate nu k^2 and the entropy
+    # rate gamma chi k^2 differ by the factor gamma, entropy decays faster
+    ent = min(rest, key=lambda z: z.real) if rest else np.nan
+    return ac, -float(np.real(ent))
+
+
 def temperature(rho, jx, jy, jz, en):
     """theta from E = (rho u^2 + 3 rho theta)/2 (Sec. II)."""
     u2 = (jx * jx + jy * jy + jz * jz) / (rho * rho)

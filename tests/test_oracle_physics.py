@@ -100,3 +100,103 @@ def test_thermal_mode_decay(orc):
     assert abs(fit["w"] / k / np.sqrt(an.GAMMA * th0) - 1) < 1e-3
     # entropy part carries 1/gamma of the initial temperature jump
     assert abs(fit["B"] / (1e-3 * th0) - 0.6) < 5e-3
+
+
+# ---------------------------------------------------------------------------
+# Linear theory of the lattice scheme (one Fourier mode, linearised about
+# rest): pinned to the NSF modes in the long-wave limit, to the oracle's own
+# nonlinear update at small amplitude, and to the exact conservation and
+# rest-state properties of the step matrix.
+# ---------------------------------------------------------------------------
+
+def _lattice(orc):
+    c, w, th = orc.lattice()
+    return np.asarray(c, dtype=float).reshape(-1, 3), np.asarray(w, dtype=float), th
+
+
+def test_linear_step_matrix_conserves_and_keeps_rest(orc):
+    """k = 0: the step conserves mass, momentum and energy (the moment rows
+    are left eigenvectors with eigenvalue 1), and the rest state w is a
+    fixed point; for omega = 1 the collision is the projection J itself."""
+    c, w, th = _lattice(orc)
+    P = np.vstack([np.ones(41), c.T, 0.5 * np.sum(c * c, axis=1)])
+    for omega in (0.6, 1.0, 1.7):
+        M = an.linear_step_matrix(c, w, [0.0, 0.0, 0.0], omega)
+        assert np.max(np.abs(P @ M - P)) < 1e-13
+        assert np.max(np.abs(M @ w - w)) < 1e-15
+    J = an.linear_step_matrix(c, w, [0.0, 0.0, 0.0], 1.0)
+    assert np.max(np.abs(J @ J - J)) < 1e-13
+    # the linearised equilibrium of a pure density change is w times it
+    # (f_eq(rho, 0, theta0) = rho w exactly)
+    assert np.max(np.abs(J @ (3.0 * w) - 3.0 * w)) < 1e-14
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.9])
+@pytest.mark.parametrize("direction", [(1, 0, 0), (1, 1, 1), (1, 2, 0)])
+def test_linear_modes_converge_to_nsf(orc, tau, direction):
+    """Long-wave limit: the scheme's hydrodynamic eigenvalues approach the
+    linearised NSF modes (sound speed sqrt(gamma theta0), acoustic and
+    entropy damping with nu = chi = theta0 (tau - 1/2)) with second-order
+    error, isotropically: c_s within 0.1% and both rates within 1% of NSF
+    from 64 cells per wavelength on, and each error falling by at least
+    3.5x per doubling of the wavelength."""
+    c, w, th = _lattice(orc)
+    nu = an.viscosity(th, tau)
+    d = np.asarray(direction, dtype=float)
+    d /= np.linalg.norm(d)
+    errs = []
+    for lam in (64, 128, 256):
+        k = 2 * np.pi / lam
+        ac, ent = an.linear_modes(c, w, k * d, 1.0 / tau)
+        nac, nent = an.nsf_modes(k, nu, nu, th)
+        e = (ac.imag / k / np.sqrt(an.GAMMA * th) - 1, -ac.real / -nac.real - 1, ent / -nent - 1)
+        errs.append(np.abs(e))
+        assert e[0] < 0 and abs(e[0]) < 1e-3 and abs(e[1]) < 1e-2 and abs(e[2]) < 1e-2, (lam, e)
+    errs = np.array(errs)
+    assert np.all(errs[:-1] / errs[1:] > 3.5), errs
+
+
+def test_linear_theory_matches_oracle_run_at_small_amplitude(orc):
+    """A random population perturbation of one oblique Fourier mode (half
+    and integer velocities all move it), 1e-7 in size, through 40 oracle
+    steps (full nonlinear collision and streaming): the five conserved
+    moment amplitudes follow the linear theory to 1e-6 of their size."""
+    c, w, th = _lattice(orc)
+    nx, ny, nz, tau = 8, 6, 4, 0.7
+    kv = 2 * np.pi * np.array([1.0 / nx, 1.0 / ny, 1.0 / nz])
+    rng = np.random.default_rng(3)
+    a = (rng.standard_normal(41) + 1j * rng.standard_normal(41)) * w
+    eps = 1e-7
+    x, y, z = an.node_positions(nx, ny, nz)
+    ph = np.exp(1j * (kv[0] * x + kv[1] * y + kv[2] * z))
+    f = w[:, None] + eps * np.real(a[:, None] * ph[None, :])
+    lin = an.linear_moment_series(c, w, kv, 1.0 / tau, 0.5 * eps * a, 40)
+    scale = np.max(np.abs(lin[0]))
+    worst = 0.0
+    for t in range(1, 41):
+        f = orc.run(nx, ny, nz, 1.0 / tau, f, 1)
+        m = orc.moment_fields(f)
+        got = np.array([an.fourier_mode(m[i], nx, ny, nz, kv) for i in range(5)])
+        worst = max(worst, float(np.max(np.abs(got - lin[t])) / scale))
+    assert worst < 1e-6, worst
+
+
+def test_linear_theory_wrong_streaming_sign_is_detected(orc):
+    """The same comparison fails with the streaming phase reversed (pull
+    instead of push) after one step: the pin separates the two."""
+    c, w, th = _lattice(orc)
+    nx, ny, nz, tau = 8, 6, 4, 0.7
+    kv = 2 * np.pi * np.array([1.0 / nx, 1.0 / ny, 1.0 / nz])
+    rng = np.random.default_rng(3)
+    a = (rng.standard_normal(41) + 1j * rng.standard_normal(41)) * w
+    eps = 1e-7
+    x, y, z = an.node_positions(nx, ny, nz)
+    ph = np.exp(1j * (kv[0] * x + kv[1] * y + kv[2] * z))
+    f = w[:, None] + eps * np.real(a[:, None] * ph[None, :])
+    f = orc.run(nx, ny, nz, 1.0 / tau, f, 1)
+    m = orc.moment_fields(f)
+    got = np.array([an.fourier_mode(m[i], nx, ny, nz, kv) for i in range(5)])
+    M = an.linear_step_matrix(c, w, -kv, 1.0 / tau)  # the reversed phase
+    P = np.vstack([np.ones(41), c.T, 0.5 * np.sum(c * c, axis=1)])
+    wrong = P @ (M @ (0.5 * eps * a))
+    assert np.max(np.abs(got - wrong)) / np.max(np.abs(got)) > 1e-2
