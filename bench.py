@@ -101,8 +101,10 @@ def time_form(lbm, torch, F, th, n, tau, form, steps, warmup, autotune):
     tune = None
     if autotune:
         best, table = ctx.autotune(reps=3)
-        tune = {"variant": best[0], "xcd_remap": best[1], "block_threads": lbm.variant_desc(best[0])[0]}
+        tune = {"variant": best[0], "xcd_remap": best[1]}
     info = ctx.info()
+    if tune is not None:
+        tune["block_threads"] = info["block_threads"]
     ctx.step(warmup)
     ctx.synchronize()
     start = torch.cuda.Event(enable_timing=True)

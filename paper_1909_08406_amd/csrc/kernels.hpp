@@ -155,6 +155,47 @@ __device__ inline void st_hint(T* p, T v, int nt)
     }
 }
 
+// Collision of one node from its decoded stored values x, encoded to the
+// storage type in out (round to nearest, or stochastic rounding with bits
+// drawn for node `nid` of the context at the launch's step); raises the
+// flag for an unrealisable node.
+template <class ST, int NEWTON, bool SR>
+__device__ inline void collide_encode(const typename ST::R x[Q], typename ST::T out[Q], const StepParams& p,
+                                      uint32_t nid)
+{
+    using R = typename ST::R;
+    CollideConst<R> cc;
+    cc.om = R(p.omega);
+    cc.rho_ref = ST::shifted ? R(p.rho_ref) : R(1);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        cc.inv_scale[s] = ST::unit_scale ? R(1) : R(p.inv_scale[s]);
+        cc.omw[s] = ST::shifted ? R(p.omw[s]) : cc.om * R(SHELL_W[s]);
+    }
+    R y[Q], rho, theta;
+    collide<R, ST::shifted, NEWTON>(x, y, cc, rho, theta);
+    flag_bad<R>(p, rho, theta);
+    uint32_t rs = 0, rw = 0;
+    if constexpr (SR) {
+        // random bits per (node of the context, step): the step is the
+        // launch's own count plus, in graph replays, a device-held base
+        const uint32_t step = p.step + (p.step_base ? *p.step_base : 0u);
+        rs = hash32(nid ^ hash32(step * 0x9e3779b9u + p.seed)) | 1u;
+    }
+    static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if constexpr (SR) {
+            if constexpr (q % 2 == 0) rw = xorshift32(rs);
+            const uint32_t rb = (q % 2 == 0) ? (rw & 0xffffu) : (rw >> 16);
+            if constexpr (ST::shifted) out[q] = ST::encode_sr(y[q], rb);
+            else out[q] = sr_add(x[q], y[q], rb);
+        } else {
+            if constexpr (ST::shifted) out[q] = ST::encode(y[q]);
+            else out[q] = ST::encode(x[q] + y[q]);
+        }
+    });
+}
+
 // The step of node n of one box: src and dst are the box's first q-block
 // in the current and the other population buffer.
 template <class ST, int NEWTON, int FL, bool SR>
@@ -174,39 +215,12 @@ __device__ inline void step_node(const char* __restrict__ src, char* __restrict_
         x[q] = ST::decode(ld_hint(reinterpret_cast<const T*>(src + q * qbytes + uint64_t(pull_src<q>(nb))),
                                   FL & FL_NT_LOAD));
     });
-
-    CollideConst<R> cc;
-    cc.om = R(p.omega);
-    cc.rho_ref = ST::shifted ? R(p.rho_ref) : R(1);
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-        cc.inv_scale[s] = ST::unit_scale ? R(1) : R(p.inv_scale[s]);
-        cc.omw[s] = ST::shifted ? R(p.omw[s]) : cc.om * R(SHELL_W[s]);
-    }
-    R y[Q], rho, theta;
-    collide<R, ST::shifted, NEWTON>(x, y, cc, rho, theta);
-    flag_bad<R>(p, rho, theta);
+    T out[Q];
+    collide_encode<ST, NEWTON, SR>(x, out, p, p.node0 + n);
     const uint32_t nbytes = n * uint32_t(sizeof(T));
-    uint32_t rs = 0, rw = 0;
-    if constexpr (SR) {
-        // random bits per (node of the context, step): the step is the
-        // launch's own count plus, in graph replays, a device-held base
-        const uint32_t step = p.step + (p.step_base ? *p.step_base : 0u);
-        rs = hash32((p.node0 + n) ^ hash32(step * 0x9e3779b9u + p.seed)) | 1u;
-    }
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        T out;
-        if constexpr (SR) {
-            if constexpr (q % 2 == 0) rw = xorshift32(rs);
-            const uint32_t rb = (q % 2 == 0) ? (rw & 0xffffu) : (rw >> 16);
-            if constexpr (ST::shifted) out = ST::encode_sr(y[q], rb);
-            else out = sr_add(x[q], y[q], rb);
-        } else {
-            if constexpr (ST::shifted) out = ST::encode(y[q]);
-            else out = ST::encode(x[q] + y[q]);
-        }
-        st_hint(reinterpret_cast<T*>(dst + q * qbytes + uint64_t(nbytes)), out, FL & FL_NT_STORE);
+        st_hint(reinterpret_cast<T*>(dst + q * qbytes + uint64_t(nbytes)), out[q], FL & FL_NT_STORE);
     });
 }
 
