@@ -56,6 +56,11 @@ def _load():
         "orc_series_errors": (None, [d, _dp]),
         "orc_equilibrium_series": (None, [d, d, d, d, d, _dp]),
         "orc_collide_node": (i, [_dp, d, _dp]),
+        "orc_equilibrium_iso": (i, [d, d, d, d, _dp, _dp, _dp, _ip]),
+        "orc_collide_node_model": (i, [_dp, d, i, _dp]),
+        "orc_init_model": (i, [i, i, i, _dp, _dp, _dp, _dp, _dp, i, _dp]),
+        "orc_collide_field_model": (i, [i, i, i, d, i, _dp, _dp]),
+        "orc_run_model": (i, [i, i, i, d, i, _dp, _dp, i]),
         "orc_pull_map": (None, [i, i, i, _lp]),
         "orc_push_map": (None, [i, i, i, _lp]),
         "orc_pull_src_nodes": (None, [i, i, i, _lp, l, _lp]),
@@ -132,6 +137,27 @@ def equilibrium(rho, u, theta):
     return feq, lam, float(res[0]), it.value, rc
 
 
+def equilibrium_iso(rho, u):
+    """Isothermal equilibrium (mass and momentum constraints only): returns
+    (feq[41], lam[5] = (alpha, beta_x, beta_y, beta_z, 0), residual,
+    newton iterations, status)."""
+    feq = np.zeros(NQ)
+    lam = np.zeros(5)
+    res = np.zeros(1)
+    it = ctypes.c_int(0)
+    rc = _load().orc_equilibrium_iso(float(rho), float(u[0]), float(u[1]), float(u[2]),
+                                     _d(feq), _d(lam), _d(res), ctypes.byref(it))
+    return feq, lam, float(res[0]), it.value, rc
+
+
+# equilibrium models: 0 energy conserving (E2), 1 isothermal
+MODELS = {"thermal": 0, "isothermal": 1}
+
+
+def _model(model):
+    return MODELS[model] if isinstance(model, str) else int(model)
+
+
 def series_rest(rho, eta):
     out = np.zeros(NQ)
     _load().orc_series_rest(float(rho), float(eta), _d(out))
@@ -151,10 +177,10 @@ def equilibrium_series(rho, u, theta):
     return out
 
 
-def collide_node(f, omega):
+def collide_node(f, omega, model="thermal"):
     f = _f64(f)
     out = np.zeros(NQ)
-    rc = _load().orc_collide_node(_d(f), float(omega), _d(out))
+    rc = _load().orc_collide_node_model(_d(f), float(omega), _model(model), _d(out))
     if rc != 0:
         raise RuntimeError("oracle equilibrium did not converge")
     return out
@@ -182,34 +208,35 @@ def push_map(nx, ny, nz):
     return out.reshape(NQ, n)
 
 
-def init(nx, ny, nz, rho, ux, uy, uz, theta):
-    """Equilibrium populations [41, N] for FP64 node fields (theta absolute)."""
+def init(nx, ny, nz, rho, ux, uy, uz, theta, model="thermal"):
+    """Equilibrium populations [41, N] for FP64 node fields (theta absolute;
+    ignored by the isothermal model)."""
     n = 2 * nx * ny * nz
     args = [_f64(a).reshape(-1) for a in (rho, ux, uy, uz, theta)]
     for a in args:
         if a.size != n:
             raise ValueError("field size %d != %d nodes" % (a.size, n))
     f = np.zeros((NQ, n))
-    rc = _load().orc_init(nx, ny, nz, *[_d(a) for a in args], _d(f))
+    rc = _load().orc_init_model(nx, ny, nz, *[_d(a) for a in args], _model(model), _d(f))
     if rc != 0:
         raise RuntimeError("oracle equilibrium did not converge at init")
     return f
 
 
-def collide_field(nx, ny, nz, omega, f):
+def collide_field(nx, ny, nz, omega, f, model="thermal"):
     f = _pops(f, 2 * nx * ny * nz)
     out = np.zeros_like(f)
-    rc = _load().orc_collide_field(nx, ny, nz, float(omega), _d(f), _d(out))
+    rc = _load().orc_collide_field_model(nx, ny, nz, float(omega), _model(model), _d(f), _d(out))
     if rc != 0:
         raise RuntimeError("oracle equilibrium did not converge")
     return out
 
 
-def run(nx, ny, nz, omega, f, nsteps):
+def run(nx, ny, nz, omega, f, nsteps, model="thermal"):
     """Advance populations f [41, N] by nsteps collide+push steps (in place copy returned)."""
     f = _pops(f, 2 * nx * ny * nz, copy=True)
     tmp = np.empty_like(f)
-    rc = _load().orc_run(nx, ny, nz, float(omega), _d(f), _d(tmp), int(nsteps))
+    rc = _load().orc_run_model(nx, ny, nz, float(omega), _model(model), _d(f), _d(tmp), int(nsteps))
     if rc != 0:
         raise RuntimeError("oracle equilibrium did not converge during run")
     return f

@@ -59,7 +59,7 @@ def fourier_mode(field, nx, ny, nz, kvec):
     return np.sum(f * ph) / f.size
 
 
-def linear_step_matrix(c, w, kvec, omega):
+def linear_step_matrix(c, w, kvec, omega, isothermal=False):
     """One step of the lattice BGK scheme, linearised about the rest state
     f_i = w_i (rho 1, u 0, theta theta0), acting on the amplitudes a_i of a
     Fourier mode a_i exp(i k.x) over the bcc node positions (Sec. II: relax
@@ -71,11 +71,13 @@ def linear_step_matrix(c, w, kvec, omega):
     d f onto span(1, c, c^2) that keeps the five conserved moments. Moving
     along c_i brings to x what was at x - c_i (a node of the bcc lattice for
     every c_i, half-integer ones included), i.e. multiplies a_i by
-    exp(-i k.c_i). Returns the 41 x 41 complex matrix S (I + omega (J - I))."""
+    exp(-i k.c_i). Returns the 41 x 41 complex matrix S (I + omega (J - I)).
+    isothermal: the equilibrium keeps mass and momentum only (phi = (1, c)),
+    the model with sound speed sqrt(theta0)."""
     c = np.asarray(c, dtype=float).reshape(-1, 3)
     w = np.asarray(w, dtype=float)
     q = w.size
-    phi = np.column_stack([np.ones(q), c, np.sum(c * c, axis=1)])
+    phi = np.column_stack([np.ones(q), c] if isothermal else [np.ones(q), c, np.sum(c * c, axis=1)])
     gram = phi.T @ (w[:, None] * phi)
     J = (w[:, None] * phi) @ np.linalg.solve(gram, phi.T)
     C = (1.0 - omega) * np.eye(q) + omega * J
@@ -83,12 +85,12 @@ def linear_step_matrix(c, w, kvec, omega):
     return S[:, None] * C
 
 
-def linear_moment_series(c, w, kvec, omega, a0, steps):
+def linear_moment_series(c, w, kvec, omega, a0, steps, isothermal=False):
     """Amplitudes of (rho, jx, jy, jz, E) of the mode after t = 0..steps
     steps of the linearised scheme from population amplitudes a0:
     array (steps + 1, 5); E = sum_i f_i c_i^2 / 2."""
     c = np.asarray(c, dtype=float).reshape(-1, 3)
-    M = linear_step_matrix(c, w, kvec, omega)
+    M = linear_step_matrix(c, w, kvec, omega, isothermal)
     P = np.vstack([np.ones(len(c)), c.T, 0.5 * np.sum(c * c, axis=1)])
     a = np.asarray(a0, dtype=complex)
     out = np.empty((steps + 1, 5), dtype=complex)
@@ -98,16 +100,18 @@ def linear_moment_series(c, w, kvec, omega, a0, steps):
     return out
 
 
-def linear_modes(c, w, kvec, omega):
+def linear_modes(c, w, kvec, omega, isothermal=False):
     """Hydrodynamic eigenvalues of the linearised step for wavevector k, as
     rates per step: (acoustic log-eigenvalue with Im > 0, entropy rate).
     The acoustic pair and the entropy mode are the eigenvalues closest to
-    exp(+-i c_s |k|) and 1 among those of modulus near 1."""
-    ev = np.linalg.eigvals(linear_step_matrix(c, w, kvec, omega))
+    exp(+-i c_s |k|) and 1 among those of modulus near 1. The isothermal
+    model has no entropy mode (its rate is then that of the slowest
+    non-propagating mode, a shear mode)."""
+    ev = np.linalg.eigvals(linear_step_matrix(c, w, kvec, omega, isothermal))
     lg = np.log(ev.astype(complex))
-    # slow modes: the five with the smallest decay (two acoustic, one
-    # entropy, two shear); acoustic ones have the largest |Im|
-    slow = lg[np.argsort(-lg.real)[:5]]
+    # slow modes, one per conserved moment: two acoustic, two shear and (with
+    # energy conserved) one entropy; the acoustic ones have the largest |Im|
+    slow = lg[np.argsort(-lg.real)[:4 if isothermal else 5]]
     ac = slow[np.argmax(slow.imag)]
     rest = [z for z in slow if abs(z.imag) < 0.5 * ac.imag]
     # entropy vs shear: for Prandtl 1 the shear rate nu k^2 and the entropy

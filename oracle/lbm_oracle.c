@@ -180,27 +180,28 @@ double orc_entropy(const double *f)
 /* Exact entropic equilibrium E2 (Sec. V)                                   */
 /* ------------------------------------------------------------------------ */
 
-/* Solve A x = b (5x5) by Gaussian elimination with partial pivoting. */
-static int solve5(double A[5][5], double b[5], double x[5])
+/* Solve A x = b (n x n, n <= 5, leading block of A) by Gaussian
+ * elimination with partial pivoting. */
+static int solve_n(int n, double A[5][5], double b[5], double x[5])
 {
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < n; ++k) {
         int p = k;
-        for (int i = k + 1; i < 5; ++i)
+        for (int i = k + 1; i < n; ++i)
             if (fabs(A[i][k]) > fabs(A[p][k])) p = i;
         if (A[p][k] == 0.0) return -1;
         if (p != k) {
-            for (int j = 0; j < 5; ++j) { double t = A[k][j]; A[k][j] = A[p][j]; A[p][j] = t; }
+            for (int j = 0; j < n; ++j) { double t = A[k][j]; A[k][j] = A[p][j]; A[p][j] = t; }
             double t = b[k]; b[k] = b[p]; b[p] = t;
         }
-        for (int i = k + 1; i < 5; ++i) {
+        for (int i = k + 1; i < n; ++i) {
             double l = A[i][k] / A[k][k];
-            for (int j = k; j < 5; ++j) A[i][j] -= l * A[k][j];
+            for (int j = k; j < n; ++j) A[i][j] -= l * A[k][j];
             b[i] -= l * b[k];
         }
     }
-    for (int i = 4; i >= 0; --i) {
+    for (int i = n - 1; i >= 0; --i) {
         double s = b[i];
-        for (int j = i + 1; j < 5; ++j) s -= A[i][j] * x[j];
+        for (int j = i + 1; j < n; ++j) s -= A[i][j] * x[j];
         x[i] = s / A[i][i];
     }
     return 0;
@@ -211,40 +212,43 @@ static int solve5(double A[5][5], double b[5], double x[5])
  *   F(lam) = sum_i w_i exp(-a - b.c_i - g c_i^2) (1, c_i, c_i^2)
  *            - (1, u, u^2 + 3 theta),
  * lam = (a, bx, by, bz, g) are the paper's (alpha, beta, gamma) for mass,
- * momentum and energy. Also fills the Jacobian J = dF/dlam when J != NULL.
+ * momentum and energy. With n = 4 only the first four constraints (mass and
+ * momentum) are imposed and g stays as given (the isothermal equilibrium,
+ * g = 0). Also fills the Jacobian J = dF/dlam when J != NULL.
  */
-static double e2_residual(const double lam[5], const double tgt[5], double F[5], double J[5][5])
+static double e2_residual(int n, const double lam[5], const double tgt[5], double F[5], double J[5][5])
 {
     double phi[5];
-    for (int k = 0; k < 5; ++k) F[k] = -tgt[k];
+    for (int k = 0; k < n; ++k) F[k] = -tgt[k];
     if (J) memset(J, 0, sizeof(double) * 25);
     for (int i = 0; i < NQ; ++i) {
         double cx = g_c[i][0], cy = g_c[i][1], cz = g_c[i][2];
         double c2 = cx * cx + cy * cy + cz * cz;
         double e = g_w[i] * exp(-lam[0] - lam[1] * cx - lam[2] * cy - lam[3] * cz - lam[4] * c2);
         phi[0] = 1.0; phi[1] = cx; phi[2] = cy; phi[3] = cz; phi[4] = c2;
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < n; ++k) {
             F[k] += e * phi[k];
             if (J)
-                for (int l = 0; l < 5; ++l) J[k][l] -= e * phi[k] * phi[l];
+                for (int l = 0; l < n; ++l) J[k][l] -= e * phi[k] * phi[l];
         }
     }
     double r = 0.0;
-    for (int k = 0; k < 5; ++k) r = fmax(r, fabs(F[k]));
+    for (int k = 0; k < n; ++k) r = fmax(r, fabs(F[k]));
     return r;
 }
 
-/* Newton iteration from lam; returns the final max-norm residual. */
-static double e2_newton(double lam[5], const double tgt[5], int *iters)
+/* Newton iteration from lam on the first n constraints; returns the final
+ * max-norm residual. */
+static double e2_newton(int n, double lam[5], const double tgt[5], int *iters)
 {
     double F[5], J[5][5], d[5], mF[5];
-    double r = e2_residual(lam, tgt, F, J);
+    double r = e2_residual(n, lam, tgt, F, J);
     int it = 0;
     for (; it < 50 && r > 1e-15 && isfinite(r); ++it) {
-        for (int k = 0; k < 5; ++k) mF[k] = -F[k];
-        if (solve5(J, mF, d) != 0) break;
-        for (int k = 0; k < 5; ++k) lam[k] += d[k];
-        double rn = e2_residual(lam, tgt, F, J);
+        for (int k = 0; k < n; ++k) mF[k] = -F[k];
+        if (solve_n(n, J, mF, d) != 0) break;
+        for (int k = 0; k < n; ++k) lam[k] += d[k];
+        double rn = e2_residual(n, lam, tgt, F, J);
         /* stop once rounding dominates: the residual no longer shrinks */
         if (!(rn < r) && r < 1e-12) { r = rn; ++it; break; }
         r = rn;
@@ -278,16 +282,47 @@ int orc_equilibrium(double rho, double ux, double uy, double uz, double theta,
         z += g_w[i] * exp(-lam[1] * cx - lam[2] * cy - lam[3] * cz - lam[4] * (cx * cx + cy * cy + cz * cz));
     }
     lam[0] = log(z);
-    double r = e2_newton(lam, tgt, iters);
+    double r = e2_newton(5, lam, tgt, iters);
     if (!(r <= 1e-13)) {
         for (int k = 0; k < 5; ++k) lam[k] = 0.0;
-        r = e2_newton(lam, tgt, iters);
+        r = e2_newton(5, lam, tgt, iters);
     }
     for (int i = 0; i < NQ; ++i) {
         double cx = g_c[i][0], cy = g_c[i][1], cz = g_c[i][2];
         double c2 = cx * cx + cy * cy + cz * cz;
         feq[i] = rho * g_w[i] * exp(-lam[0] - lam[1] * cx - lam[2] * cy - lam[3] * cz - lam[4] * c2);
     }
+    if (lam_out) for (int k = 0; k < 5; ++k) lam_out[k] = lam[k];
+    if (resid) *resid = r;
+    return (r <= 1e-13) ? 0 : -1;
+}
+
+/*
+ * Isothermal equilibrium (Sec. V: the usual construction, with mass and
+ * momentum but not energy conserved; Sec. VI uses it for the isothermal
+ * acoustic pulse): f_eq,i = rho w_i exp(-a - b.c_i), the minimiser of the
+ * same H-function under the mass and momentum constraints alone, so that
+ * g = 0 and the rest state is f = rho w at temperature theta0. Newton on
+ * (a, bx, by, bz) from b = -u/theta0, then from lam = 0 if that fails.
+ * Returns 0 on success, -1 if not converged.
+ */
+int orc_equilibrium_iso(double rho, double ux, double uy, double uz, double *feq, double *lam_out, double *resid,
+                        int *iters)
+{
+    lattice_build();
+    double tgt[5] = {1.0, ux, uy, uz, 0.0};
+    double lam[5] = {0.0, -ux / g_theta0, -uy / g_theta0, -uz / g_theta0, 0.0};
+    double z = 0.0;
+    for (int i = 0; i < NQ; ++i)
+        z += g_w[i] * exp(-lam[1] * g_c[i][0] - lam[2] * g_c[i][1] - lam[3] * g_c[i][2]);
+    lam[0] = log(z);
+    double r = e2_newton(4, lam, tgt, iters);
+    if (!(r <= 1e-13)) {
+        for (int k = 0; k < 5; ++k) lam[k] = 0.0;
+        r = e2_newton(4, lam, tgt, iters);
+    }
+    for (int i = 0; i < NQ; ++i)
+        feq[i] = rho * g_w[i] * exp(-lam[0] - lam[1] * g_c[i][0] - lam[2] * g_c[i][1] - lam[3] * g_c[i][2]);
     if (lam_out) for (int k = 0; k < 5; ++k) lam_out[k] = lam[k];
     if (resid) *resid = r;
     return (r <= 1e-13) ? 0 : -1;
@@ -383,18 +418,30 @@ void orc_equilibrium_series(double rho, double ux, double uy, double uz, double 
 /* Collision (Sec. II, discrete BGK)                                        */
 /* ------------------------------------------------------------------------ */
 
-/* f* = f + omega (f_eq(rho(f), u(f), theta(f)) - f) for one node. */
-int orc_collide_node(const double *f, double omega, double *out)
+/* f* = f + omega (f_eq - f) for one node (Sec. II), with the equilibrium of
+ * the node's rho, u, theta (model 0, energy conserving) or of its rho, u
+ * (model 1, isothermal). */
+int orc_collide_node_model(const double *f, double omega, int model, double *out)
 {
     double m[5], feq[NQ];
     orc_node_moments(f, m);
     double rho = m[0];
     double ux = m[1] / rho, uy = m[2] / rho, uz = m[3] / rho;
-    /* E = (rho u^2 + 3 rho theta)/2 (Sec. II) */
-    double theta = (2.0 * m[4] / rho - (ux * ux + uy * uy + uz * uz)) / 3.0;
-    int rc = orc_equilibrium(rho, ux, uy, uz, theta, feq, NULL, NULL, NULL);
+    int rc;
+    if (model == 1) {
+        rc = orc_equilibrium_iso(rho, ux, uy, uz, feq, NULL, NULL, NULL);
+    } else {
+        /* E = (rho u^2 + 3 rho theta)/2 (Sec. II) */
+        double theta = (2.0 * m[4] / rho - (ux * ux + uy * uy + uz * uz)) / 3.0;
+        rc = orc_equilibrium(rho, ux, uy, uz, theta, feq, NULL, NULL, NULL);
+    }
     for (int i = 0; i < NQ; ++i) out[i] = f[i] + omega * (feq[i] - f[i]);
     return rc;
+}
+
+int orc_collide_node(const double *f, double omega, double *out)
+{
+    return orc_collide_node_model(f, omega, 0, out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -473,9 +520,10 @@ void orc_push_map(int nx, int ny, int nz, int64_t *dst)
         }
 }
 
-/* Populations at equilibrium with the given fields (all [node], FP64). */
-int orc_init(int nx, int ny, int nz, const double *rho, const double *ux, const double *uy,
-             const double *uz, const double *theta, double *f)
+/* Populations at equilibrium with the given fields (all [node], FP64);
+ * model 1 (isothermal) ignores theta. */
+int orc_init_model(int nx, int ny, int nz, const double *rho, const double *ux, const double *uy,
+                   const double *uz, const double *theta, int model, double *f)
 {
     lattice_build();
     int64_t N = 2LL * nx * ny * nz;
@@ -483,14 +531,22 @@ int orc_init(int nx, int ny, int nz, const double *rho, const double *ux, const 
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int64_t n = 0; n < N; ++n) {
         double feq[NQ];
-        if (orc_equilibrium(rho[n], ux[n], uy[n], uz[n], theta[n], feq, NULL, NULL, NULL) != 0) bad = 1;
+        int rc = model == 1 ? orc_equilibrium_iso(rho[n], ux[n], uy[n], uz[n], feq, NULL, NULL, NULL)
+                            : orc_equilibrium(rho[n], ux[n], uy[n], uz[n], theta[n], feq, NULL, NULL, NULL);
+        if (rc != 0) bad = 1;
         for (int q = 0; q < NQ; ++q) f[q * N + n] = feq[q];
     }
     return bad ? -1 : 0;
 }
 
+int orc_init(int nx, int ny, int nz, const double *rho, const double *ux, const double *uy,
+             const double *uz, const double *theta, double *f)
+{
+    return orc_init_model(nx, ny, nz, rho, ux, uy, uz, theta, 0, f);
+}
+
 /* Post-collision populations of every node, without streaming. */
-int orc_collide_field(int nx, int ny, int nz, double omega, const double *f, double *out)
+int orc_collide_field_model(int nx, int ny, int nz, double omega, int model, const double *f, double *out)
 {
     lattice_build();
     int64_t N = 2LL * nx * ny * nz;
@@ -499,17 +555,22 @@ int orc_collide_field(int nx, int ny, int nz, double omega, const double *f, dou
     for (int64_t n = 0; n < N; ++n) {
         double a[NQ], b[NQ];
         for (int q = 0; q < NQ; ++q) a[q] = f[q * N + n];
-        if (orc_collide_node(a, omega, b) != 0) bad = 1;
+        if (orc_collide_node_model(a, omega, model, b) != 0) bad = 1;
         for (int q = 0; q < NQ; ++q) out[q * N + n] = b[q];
     }
     return bad ? -1 : 0;
+}
+
+int orc_collide_field(int nx, int ny, int nz, double omega, const double *f, double *out)
+{
+    return orc_collide_field_model(nx, ny, nz, omega, 0, f, out);
 }
 
 /*
  * nsteps time steps: collide at every node, then push along the links.
  * f holds the state on entry and on exit; tmp is scratch of the same size.
  */
-int orc_run(int nx, int ny, int nz, double omega, double *f, double *tmp, int nsteps)
+int orc_run_model(int nx, int ny, int nz, double omega, int model, double *f, double *tmp, int nsteps)
 {
     lattice_build();
     int64_t N = 2LL * nx * ny * nz;
@@ -520,12 +581,17 @@ int orc_run(int nx, int ny, int nz, double omega, double *f, double *tmp, int ns
             double a[NQ], b[NQ];
             int64_t x = n % nx, y = (n / nx) % ny, z = (n / ((int64_t)nx * ny)) % nz, s = n / ((int64_t)nx * ny * nz);
             for (int q = 0; q < NQ; ++q) a[q] = f[q * N + n];
-            if (orc_collide_node(a, omega, b) != 0) bad = 1;
+            if (orc_collide_node_model(a, omega, model, b) != 0) bad = 1;
             for (int q = 0; q < NQ; ++q) tmp[q * N + push_dest(q, s, x, y, z, nx, ny, nz)] = b[q];
         }
         memcpy(f, tmp, sizeof(double) * (size_t)(NQ * N));
     }
     return bad ? -1 : 0;
+}
+
+int orc_run(int nx, int ny, int nz, double omega, double *f, double *tmp, int nsteps)
+{
+    return orc_run_model(nx, ny, nz, omega, 0, f, tmp, nsteps);
 }
 
 /* Per-node rho, j, E fields. */

@@ -169,3 +169,78 @@ def test_series_equilibrium_momentum_error_is_anisotropic_cubic(orc):
     u = np.array([0.01, -0.02, 0.005])
     f = orc.equilibrium_series(1.0, u, t0)
     assert np.max(np.abs(f @ c - u)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Isothermal equilibrium: the same H-minimiser with the mass and momentum
+# constraints only (Sec. V; used by the paper's isothermal acoustic pulse,
+# Sec. VI).
+# ---------------------------------------------------------------------------
+
+def test_iso_conserves_mass_and_momentum(orc):
+    c, w, t0 = orc.lattice()
+    for rho, u, _ in _cases(seed=5):
+        f, lam, res, it, rc = orc.equilibrium_iso(rho, u)
+        assert rc == 0 and it <= 6
+        assert abs(f.sum() / rho - 1) < 1e-14
+        assert np.max(np.abs(f @ c / rho - u)) < 1e-14
+        assert lam[4] == 0.0
+
+
+def test_iso_has_the_exponential_form_without_c2(orc):
+    """log(f_eq / (rho w)) is exactly affine in (1, c): no c^2 multiplier."""
+    c, w, t0 = orc.lattice()
+    phi = np.column_stack([np.ones(41), c])
+    for rho, u, _ in _cases(seed=6, n=10):
+        f, lam, *_ = orc.equilibrium_iso(rho, u)
+        y = np.log(f / (rho * w))
+        assert np.max(np.abs(y + phi @ lam[:4])) < 1e-13
+
+
+def test_iso_rest_state_is_rho_w_at_theta0(orc):
+    c, w, t0 = orc.lattice()
+    f, lam, *_ = orc.equilibrium_iso(0.7, (0.0, 0.0, 0.0))
+    assert np.max(np.abs(lam)) < 1e-15
+    assert np.max(np.abs(f - 0.7 * w)) < 1e-16
+    # its kinetic temperature is theta0
+    assert abs((f @ (c ** 2).sum(1)) / (3 * 0.7) / t0 - 1) < 1e-14
+
+
+def test_iso_minimises_H_under_mass_and_momentum(orc):
+    c, w, t0 = orc.lattice()
+    phi = np.column_stack([np.ones(41), c])
+    q, _ = np.linalg.qr(phi, mode="complete")
+    null = q[:, 4:]
+    rng = np.random.default_rng(7)
+    for rho, u, _ in _cases(seed=8, n=8):
+        f, *_ = orc.equilibrium_iso(rho, u)
+        h0 = orc.entropy(f)
+        for _ in range(20):
+            d = null @ rng.normal(size=37)
+            d *= 1e-3 * f.min() / np.max(np.abs(d))
+            assert orc.entropy(f + d) > h0
+
+
+def test_iso_pressure_tensor_is_isothermal_euler_to_fourth_order(orc):
+    """P = rho theta0 delta + rho u u up to O(u^4): the isothermal Euler
+    stress with sound speed sqrt(theta0)."""
+    c, w, t0 = orc.lattice()
+    errs = []
+    for s in (0.025, 0.05, 0.1):
+        u = np.array([0.6, -0.8, 0.0]) * s
+        f, *_ = orc.equilibrium_iso(1.0, u)
+        P = np.einsum("q,qa,qb->ab", f, c, c)
+        errs.append(np.max(np.abs(P - (t0 * np.eye(3) + np.outer(u, u)))))
+    assert errs[2] < 2e-5
+    assert 12 < errs[1] / errs[0] < 20 and 12 < errs[2] / errs[1] < 20
+
+
+def test_iso_collision_keeps_mass_and_momentum_not_energy(orc):
+    c, w, t0 = orc.lattice()
+    rng = np.random.default_rng(9)
+    f = w * (1 + 0.05 * rng.standard_normal(41))
+    out = orc.collide_node(f, 1.0 / 0.7, model="isothermal")
+    m_in, m_out = orc.node_moments(f), orc.node_moments(out)
+    assert np.max(np.abs(m_out[:4] - m_in[:4])) < 1e-15
+    # energy relaxes toward the equilibrium's (temperature theta0 at rest)
+    assert abs(m_out[4] - m_in[4]) > 1e-6
