@@ -72,6 +72,13 @@ typedef enum {
 /* lbm_opts.flags */
 #define LBM_FLAG_STOCHASTIC_ROUNDING 1u /* round stored values stochastically (unbiased):
                                            LBM_F32, LBM_F16_SHIFT, LBM_BF16_SHIFT only */
+#define LBM_FLAG_ISOTHERMAL 2u          /* isothermal model (Sec. V, the usual construction
+                                           without energy conservation; Sec. VI, isothermal
+                                           acoustics): the same exponential equilibrium under
+                                           the mass and momentum constraints only, i.e. no c^2
+                                           multiplier and temperature theta0; sound speed
+                                           sqrt(theta0). The theta field of lbm_init is
+                                           checked but not used. */
 
 /* Meaning of lbm_box.tau. */
 typedef enum {
@@ -282,9 +289,11 @@ int lbm_selftest(void);
  * Sec. V), run on the host with the same arithmetic in FP64 (precision 0)
  * or FP32 (precision 1) and `newton` Newton steps: f_out = C[f_in] for one
  * node's 41 populations (direct storage; inputs rounded to the precision).
+ * flags: 0, or LBM_FLAG_ISOTHERMAL for the isothermal equilibrium.
  * For testing the arithmetic without a device. Errors: LBM_E_ARG.
  */
-int lbm_collide_host(int32_t precision, int32_t newton, double omega, const double *f_in, double *f_out);
+int lbm_collide_host(int32_t precision, int32_t newton, uint32_t flags, double omega, const double *f_in,
+                     double *f_out);
 
 #ifdef __cplusplus
 }

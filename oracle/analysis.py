@@ -174,6 +174,28 @@ def pulse_3d(r, t, eps, b, cs):
     return np.where(r < 1e-12, lim, v)
 
 
+def pulse_2d(r, t, eps, b, cs, nu_eff=0.0):
+    """Axisymmetric 2D pulse eps exp(-alpha r^2), alpha = ln2/b^2, under
+    the linearised Euler equations with sound speed cs (Sec. VI, the 2D
+    acoustic pulse): the Hankel-transform solution
+        rho'(r, t) = eps/(2 alpha) int_0^inf e^{-xi^2/(4 alpha)} cos(cs xi t)
+                     J0(xi r) xi d xi,
+    with an optional viscous damping factor e^{-nu_eff xi^2 t} (nu_eff the
+    acoustic attenuation coefficient Gamma/k^2)."""
+    from scipy import special
+    alpha = np.log(2.0) / (b * b)
+    upper = 14.0 * np.sqrt(alpha)
+    r = np.atleast_1d(np.asarray(r, dtype=float))
+
+    def one(rr):
+        fn = lambda xi: (np.exp(-xi * xi / (4.0 * alpha) - nu_eff * xi * xi * t) * np.cos(cs * xi * t)
+                         * special.j0(xi * rr) * xi)
+        val, _ = integrate.quad(fn, 0.0, upper, limit=400, epsabs=1e-14, epsrel=1e-11)
+        return eps / (2.0 * alpha) * val
+
+    return np.array([one(rr) for rr in r])
+
+
 def pulse_3d_integral(r, t, eps, b, cs, nu_eff=0.0):
     """The same solution as the integral over wavenumbers xi,
         eps/(2 alpha sqrt(pi alpha)) int_0^inf e^{-xi^2/(4 alpha)} cos(cs xi t)

@@ -334,7 +334,10 @@ __host__ __device__ inline R kappa_of(const NodeDev<R>& st, const Shells<R>& S)
     return (st.drho - st.rho_ref * S.zeta) / (st.rho_ref * S.Z);
 }
 
-template <typename R>
+// One Newton step on the multipliers. ENERGY: the five constraints of the
+// energy-conserving equilibrium (unknowns b and g); otherwise mass and
+// momentum only (the isothermal equilibrium: unknowns b, g stays 0).
+template <typename R, bool ENERGY = true>
 __host__ __device__ inline void newton_step(Mult<R>& m, const NodeDev<R>& st)
 {
     Shells<R> S;
@@ -387,6 +390,25 @@ __host__ __device__ inline void newton_step(Mult<R>& m, const NodeDev<R>& st)
     const R r0 = (st.rho_ref * (R(1) + kap) * M[0] - st.j[0]) * st.irho;
     const R r1 = (st.rho_ref * (R(1) + kap) * M[1] - st.j[1]) * st.irho;
     const R r2 = (st.rho_ref * (R(1) + kap) * M[2] - st.j[2]) * st.irho;
+    if constexpr (!ENERGY) {
+        // 3x3 covariance of c under the equilibrium, LDL^T solve
+        const R mu0 = M[0] * iz, mu1 = M[1] * iz, mu2 = M[2] * iz;
+        const R H00 = XX[0] * iz - mu0 * mu0, H11 = XX[1] * iz - mu1 * mu1, H22 = XX[2] * iz - mu2 * mu2;
+        const R H10 = XYxy * iz - mu1 * mu0, H20 = XYxz * iz - mu2 * mu0, H21 = XYyz * iz - mu2 * mu1;
+        const R iD0 = d_rcp<R>(H00);
+        const R l10 = H10 * iD0, l20 = H20 * iD0;
+        const R D1 = H11 - l10 * H10, iD1 = d_rcp<R>(D1);
+        const R l21 = (H21 - l20 * H10) * iD1;
+        const R D2 = H22 - l20 * H20 - l21 * l21 * D1, iD2 = d_rcp<R>(D2);
+        const R y0 = r0, y1 = r1 - l10 * y0, y2 = r2 - l20 * y0 - l21 * y1;
+        const R x2 = y2 * iD2;
+        const R x1 = y1 * iD1 - l21 * x2;
+        const R x0 = y0 * iD0 - l10 * x1 - l20 * x2;
+        m.b[0] -= x0;
+        m.b[1] -= x1;
+        m.b[2] -= x2;
+        return;
+    }
     const R r3 = (st.de2 - st.rho_ref * (eta2 + kap * N2)) * st.irho;
 
     const R mu0 = M[0] * iz, mu1 = M[1] * iz, mu2 = M[2] * iz, m2 = N2 * iz;
@@ -614,6 +636,7 @@ struct StepParams {
     uint32_t seed;
     uint32_t node0;        // index of the box's first node in the context (random-bit stream)
     const uint32_t* step_base;  // null, or a device counter added to step (graph replays)
+    uint32_t isothermal;   // 1: equilibrium under mass and momentum only (temperature theta0)
 };
 
 // Counter-based random bits for stochastic rounding: one hash per node and

@@ -47,6 +47,7 @@ struct CollideConst {
     R rho_ref;       // rho0 (shifted storage) or 1
     R inv_scale[6];  // 2^{-k_s} (shifted) or 1
     R omw[6];        // omega w_s rho_ref 2^{k_s} (shifted) or omega w_s
+    bool iso;        // isothermal equilibrium (mass and momentum only)
 };
 
 template <typename R, bool SHIFTED, int NEWTON>
@@ -91,13 +92,23 @@ __host__ __device__ inline void collide(const R x[Q], R y[Q], const CollideConst
     theta_out = theta;
 
     Mult<R> m;
-    const R ith = R(1) / theta;
-    m.b[0] = ux * ith;
-    m.b[1] = uy * ith;
-    m.b[2] = uz * ith;
-    m.g = R(0.5) * ith - R(0.5 / THETA0);
+    if (cc.iso) {
+        // isothermal: g = 0, Maxwellian guess at theta0
+        m.b[0] = ux * R(1.0 / THETA0);
+        m.b[1] = uy * R(1.0 / THETA0);
+        m.b[2] = uz * R(1.0 / THETA0);
+        m.g = R(0);
 #pragma unroll
-    for (int it = 0; it < NEWTON; ++it) newton_step<R>(m, st);
+        for (int it = 0; it < NEWTON; ++it) newton_step<R, false>(m, st);
+    } else {
+        const R ith = R(1) / theta;
+        m.b[0] = ux * ith;
+        m.b[1] = uy * ith;
+        m.b[2] = uz * ith;
+        m.g = R(0.5) * ith - R(0.5 / THETA0);
+#pragma unroll
+        for (int it = 0; it < NEWTON; ++it) newton_step<R>(m, st);
+    }
 
     // f_eq,q - w_q rho_ref = w_q rho_ref D_q with 1 + D_q = (1 + eps_q)(1 + kappa)
     Shells<R> S;
@@ -167,6 +178,7 @@ __device__ inline void collide_encode(const typename ST::R x[Q], typename ST::T 
     CollideConst<R> cc;
     cc.om = R(p.omega);
     cc.rho_ref = ST::shifted ? R(p.rho_ref) : R(1);
+    cc.iso = p.isothermal != 0;
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
         cc.inv_scale[s] = ST::unit_scale ? R(1) : R(p.inv_scale[s]);
@@ -281,8 +293,9 @@ constexpr int INIT_NEWTON = 6;
 
 // Deviations D_q (f_eq,q = w_q rho_ref (1 + D_q)) of the equilibrium of
 // (rho, u, theta) in FP64, relative to the reference state w_q rho_ref.
+// iso: the isothermal equilibrium of (rho, u) (theta unused).
 __device__ inline void equilibrium_dev_f64(double rho, double ux, double uy, double uz, double theta,
-                                           double rho_ref, double D[Q])
+                                           double rho_ref, bool iso, double D[Q])
 {
     NodeDev<double> st;
     st.rho_ref = rho_ref;
@@ -294,11 +307,19 @@ __device__ inline void equilibrium_dev_f64(double rho, double ux, double uy, dou
     st.j[2] = rho * uz;
     st.de2 = rho * (ux * ux + uy * uy + uz * uz + 3.0 * theta) - rho_ref * SUM_WC2;
     Mult<double> m;
-    m.b[0] = ux / theta;
-    m.b[1] = uy / theta;
-    m.b[2] = uz / theta;
-    m.g = 0.5 / theta - 0.5 / THETA0;
-    for (int it = 0; it < INIT_NEWTON; ++it) newton_step<double>(m, st);
+    if (iso) {
+        m.b[0] = ux / THETA0;
+        m.b[1] = uy / THETA0;
+        m.b[2] = uz / THETA0;
+        m.g = 0.0;
+        for (int it = 0; it < INIT_NEWTON; ++it) newton_step<double, false>(m, st);
+    } else {
+        m.b[0] = ux / theta;
+        m.b[1] = uy / theta;
+        m.b[2] = uz / theta;
+        m.g = 0.5 / theta - 0.5 / THETA0;
+        for (int it = 0; it < INIT_NEWTON; ++it) newton_step<double>(m, st);
+    }
     Shells<double> S;
     shells_at<double>(m, S);
     const double kap = kappa_of<double>(st, S);
@@ -336,7 +357,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(typename ST::T* __restrict__ f, 
         // storage reference: rho0 for the shifted forms, the weights themselves otherwise
         const double rref = ST::shifted ? p.rho_ref : 1.0;
         double D[Q];
-        equilibrium_dev_f64(rho, ux, uy, uz, th, rref, D);
+        equilibrium_dev_f64(rho, ux, uy, uz, th, rref, p.isothermal != 0, D);
         bool bad = false;
         static_for<Q>([&](auto qc) {
             constexpr int q = decltype(qc)::value;

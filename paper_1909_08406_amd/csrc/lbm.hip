@@ -75,7 +75,7 @@ int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
     if (eb == 0) return LBM_E_ARG;
     if (opts->tau_conv != LBM_TAU_LB && opts->tau_conv != LBM_TAU_PAPER) return LBM_E_ARG;
     if (opts->newton_iters < 0 || opts->newton_iters > 4) return LBM_E_ARG;
-    if (opts->flags & ~uint32_t(LBM_FLAG_STOCHASTIC_ROUNDING)) return LBM_E_ARG;
+    if (opts->flags & ~uint32_t(LBM_FLAG_STOCHASTIC_ROUNDING | LBM_FLAG_ISOTHERMAL)) return LBM_E_ARG;
     if ((opts->flags & LBM_FLAG_STOCHASTIC_ROUNDING) &&
         !(opts->storage == LBM_F32 || opts->storage == LBM_F16_SHIFT || opts->storage == LBM_BF16_SHIFT))
         return LBM_E_ARG;
@@ -394,11 +394,12 @@ void set_shift(lbm_ctx* ctx)
 
 namespace {
 template <typename R, int NEWTON>
-void collide_host(double omega, const double* in, double* out)
+void collide_host(double omega, bool iso, const double* in, double* out)
 {
     CollideConst<R> cc;
     cc.om = R(omega);
     cc.rho_ref = R(1);
+    cc.iso = iso;
     for (int s = 0; s < 6; ++s) {
         cc.inv_scale[s] = R(1);
         cc.omw[s] = cc.om * R(SHELL_W[s]);
@@ -513,6 +514,7 @@ int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts
 
     ctx->base.flag = ctx->flag;
     ctx->base.xcd_remap = 1;
+    ctx->base.isothermal = (opts->flags & LBM_FLAG_ISOTHERMAL) ? 1u : 0u;
     ctx->base.seed = opts->seed;
     ctx->base.rho_ref = shifted ? ctx->rho0 : 0.0;
     ctx->rho_ref_storage = ctx->base.rho_ref;
@@ -806,7 +808,7 @@ int lbm_get_info(lbm_ctx* ctx, lbm_info* info)
     info->storage = ctx->storage;
     info->newton_iters = ctx->newton;
     info->shift_exp = (ctx->storage == LBM_F16_SHIFT || ctx->storage == LBM_BF16_SHIFT) ? ctx->kamp : 0;
-    info->flags = ctx->stochastic ? LBM_FLAG_STOCHASTIC_ROUNDING : 0u;
+    info->flags = (ctx->stochastic ? LBM_FLAG_STOCHASTIC_ROUNDING : 0u) | (ctx->base.isothermal ? LBM_FLAG_ISOTHERMAL : 0u);
     info->steps_done = ctx->steps_done;
     info->nboxes = int32_t(ctx->boxes.size());
     info->nodes = int64_t(ctx->L.elems / Q);
@@ -934,24 +936,28 @@ const char* lbm_strerror(int code)
     }
 }
 
-int lbm_collide_host(int32_t precision, int32_t newton, double omega, const double* f_in, double* f_out)
+int lbm_collide_host(int32_t precision, int32_t newton, uint32_t flags, double omega, const double* f_in,
+                     double* f_out)
 {
-    if (!f_in || !f_out || (precision != 0 && precision != 1) || newton < 0 || newton > 4) return LBM_E_ARG;
+    if (!f_in || !f_out || (precision != 0 && precision != 1) || newton < 0 || newton > 4 ||
+        (flags & ~uint32_t(LBM_FLAG_ISOTHERMAL)))
+        return LBM_E_ARG;
+    const bool iso = (flags & LBM_FLAG_ISOTHERMAL) != 0;
     if (precision == 0) {
         switch (newton) {
-            case 0: collide_host<double, 0>(omega, f_in, f_out); break;
-            case 1: collide_host<double, 1>(omega, f_in, f_out); break;
-            case 2: collide_host<double, 2>(omega, f_in, f_out); break;
-            case 3: collide_host<double, 3>(omega, f_in, f_out); break;
-            default: collide_host<double, 4>(omega, f_in, f_out); break;
+            case 0: collide_host<double, 0>(omega, iso, f_in, f_out); break;
+            case 1: collide_host<double, 1>(omega, iso, f_in, f_out); break;
+            case 2: collide_host<double, 2>(omega, iso, f_in, f_out); break;
+            case 3: collide_host<double, 3>(omega, iso, f_in, f_out); break;
+            default: collide_host<double, 4>(omega, iso, f_in, f_out); break;
         }
     } else {
         switch (newton) {
-            case 0: collide_host<float, 0>(omega, f_in, f_out); break;
-            case 1: collide_host<float, 1>(omega, f_in, f_out); break;
-            case 2: collide_host<float, 2>(omega, f_in, f_out); break;
-            case 3: collide_host<float, 3>(omega, f_in, f_out); break;
-            default: collide_host<float, 4>(omega, f_in, f_out); break;
+            case 0: collide_host<float, 0>(omega, iso, f_in, f_out); break;
+            case 1: collide_host<float, 1>(omega, iso, f_in, f_out); break;
+            case 2: collide_host<float, 2>(omega, iso, f_in, f_out); break;
+            case 3: collide_host<float, 3>(omega, iso, f_in, f_out); break;
+            default: collide_host<float, 4>(omega, iso, f_in, f_out); break;
         }
     }
     return LBM_OK;

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 NQ = 41
 F64, F32, F16_SHIFT, BF16_SHIFT, F32_SHIFT = 0, 1, 2, 3, 4
 FLAG_STOCHASTIC_ROUNDING = 1
+FLAG_ISOTHERMAL = 2
 TAU_LB, TAU_PAPER = 0, 1
 SHIFT_AUTO = -1000
 STORAGE = {"f64": F64, "f32": F32, "f16s": F16_SHIFT, "bf16s": BF16_SHIFT, "f32s": F32_SHIFT}
@@ -91,7 +92,7 @@ SIGNATURES = {
     "lbm_free": (None, [_vp]),
     "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "lbm_selftest": (ctypes.c_int, []),
-    "lbm_collide_host": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _dp, _dp]),
+    "lbm_collide_host": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double, _dp, _dp]),
 }
 
 _lib = None
@@ -139,17 +140,17 @@ def _boxes(boxes):
     return arr
 
 
-def _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic=False, seed=0):
+def _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic=False, seed=0, isothermal=False):
     st = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    flags = (FLAG_STOCHASTIC_ROUNDING if stochastic else 0) | (FLAG_ISOTHERMAL if isothermal else 0)
     return Opts(st, int(tau_conv), float(rho0), int(newton_iters),
-                SHIFT_AUTO if shift_exp is None else int(shift_exp),
-                FLAG_STOCHASTIC_ROUNDING if stochastic else 0, int(seed) & 0xffffffff)
+                SHIFT_AUTO if shift_exp is None else int(shift_exp), flags, int(seed) & 0xffffffff)
 
 
 def workspace_size(boxes, storage="f32", tau_conv=TAU_LB, rho0=1.0, newton_iters=0, shift_exp=None,
-                   stochastic=False):
+                   stochastic=False, isothermal=False):
     bx = _boxes(boxes)
-    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic)
+    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, 0, isothermal)
     out = ctypes.c_uint64(0)
     _check(lib().lbm_workspace_size(bx, len(boxes), ctypes.byref(op), ctypes.byref(out)), "lbm_workspace_size")
     return int(out.value)
@@ -290,13 +291,14 @@ class Context:
 
 
 def init(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0, newton_iters=0,
-         shift_exp=None, stream=None, torch_workspace=True, stochastic=False, seed=0):
+         shift_exp=None, stream=None, torch_workspace=True, stochastic=False, seed=0, isothermal=False):
     """lbm_init. boxes: [(nx, ny, nz, tau), ...]; nodal FP64 fields of all
-    boxes concatenated (theta absolute). stream: a torch.cuda.Stream (or
-    None for the library's own). With torch_workspace the device memory is a
-    torch uint8 tensor held by the returned Context."""
+    boxes concatenated (theta absolute; not used by the isothermal model).
+    stream: a torch.cuda.Stream (or None for the library's own). With
+    torch_workspace the device memory is a torch uint8 tensor held by the
+    returned Context."""
     bx = _boxes(boxes)
-    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, seed)
+    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, seed, isothermal)
     arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (rho, ux, uy, uz, theta)]
     nodes = sum(2 * b[0] * b[1] * b[2] for b in boxes)
     for a in arrs:
@@ -306,7 +308,7 @@ def init(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0
     ws_ptr, ws_bytes = None, 0
     if torch_workspace:
         import torch
-        ws_bytes = workspace_size(boxes, storage, tau_conv, rho0, newton_iters, shift_exp, stochastic)
+        ws_bytes = workspace_size(boxes, storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, isothermal)
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
         ws_ptr = ws.data_ptr()
     sptr = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
@@ -321,13 +323,14 @@ def selftest():
     return int(lib().lbm_selftest())
 
 
-def collide_host(f, omega, precision="f32", newton=None):
+def collide_host(f, omega, precision="f32", newton=None, isothermal=False):
     """The kernel's per-node collision run on the host (FP64 or FP32)."""
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(NQ)
     out = np.zeros(NQ)
     pr = {"f64": 0, "f32": 1}[precision]
     nt = (3 if pr == 0 else 1) if newton is None else int(newton)
-    _check(lib().lbm_collide_host(pr, nt, float(omega), _d(f), _d(out)), "lbm_collide_host")
+    _check(lib().lbm_collide_host(pr, nt, FLAG_ISOTHERMAL if isothermal else 0, float(omega), _d(f), _d(out)),
+           "lbm_collide_host")
     return out
 
 

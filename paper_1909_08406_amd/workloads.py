@@ -102,6 +102,22 @@ def gaussian_pulse(nx, ny=None, nz=None, eps=1e-3, b=8.0):
     return Fields(nx, ny, nz, rho, ux, uy, uz, th)
 
 
+def gaussian_pulse_2d(nx, ny, nz=1, eps=1e-3, b=8.0):
+    """2D pulse rho = 1 + eps exp(-ln2 r^2 / b^2) with r the distance in the
+    x-y plane from (nx/2, ny/2) (periodic minimum image), the same at every
+    z (one cell in z holds the two node layers of the bcc lattice); u = 0,
+    theta = theta0."""
+    x, y, z = positions(nx, ny, nz)
+    r2 = np.zeros_like(x)
+    for p, n in ((x, nx), (y, ny)):
+        d = p - 0.5 * n
+        d = d - n * np.round(d / n)
+        r2 += d * d
+    rho = 1.0 + eps * np.exp(-np.log(2.0) * r2 / (b * b))
+    _, ux, uy, uz, th = _rest(nx, ny, nz)
+    return Fields(nx, ny, nz, rho, ux, uy, uz, th)
+
+
 def random_state(nx, ny, nz, seed=0, amp_rho=1e-2, amp_u=5e-2, amp_theta=2e-2):
     """Independent uniform perturbations per node (parity-test input):
     rho = 1 + U(-a, a), u_a = U(-b, b), theta/theta0 = 1 + U(-c, c)."""

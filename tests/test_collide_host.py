@@ -48,3 +48,20 @@ def test_fp32_collision_has_no_drift_at_equilibrium(orc):
     m0, m1 = _moments(f, c), _moments(g, c)
     assert np.max(np.abs(g - f)) < 2e-8
     assert abs(m1[0] - m0[0]) < 5e-8 and abs(m1[4] - m0[4]) < 1e-7
+
+
+@pytest.mark.parametrize("precision,newton,tol,cons_tol", [("f64", 3, 2e-15, 1e-15), ("f32", 1, 4e-8, 6e-8)])
+def test_host_isothermal_collision_matches_oracle(orc, precision, newton, tol, cons_tol):
+    """Isothermal model: the kernel's collision towards the equilibrium
+    under mass and momentum only, against the oracle's; mass and momentum
+    kept to the rounding of the arithmetic."""
+    c, w, th = orc.lattice()
+    for amp, f in _cases(orc, seed=3):
+        fin = f.astype(np.float32).astype(np.float64) if precision == "f32" else f
+        g = L.collide_host(f, 1 / 0.6, precision, newton, isothermal=True)
+        ref = orc.collide_node(fin, 1 / 0.6, model="isothermal")
+        assert np.max(np.abs(g - ref)) < tol, amp
+        assert np.max(np.abs(_moments(g, c)[:4] - _moments(fin, c)[:4])) < cons_tol, amp
+    # the rest state rho w is a fixed point
+    g = L.collide_host(1.2 * w, 1 / 0.6, precision, newton, isothermal=True)
+    assert np.max(np.abs(g - 1.2 * w)) < tol

@@ -1,0 +1,171 @@
+"""The isothermal model on the GPU (LBM_FLAG_ISOTHERMAL): the same fused
+step with the equilibrium under mass and momentum only (Sec. V), and the
+paper's acoustic checks of Sec. VI: the 2D isothermal pulse against its
+Hankel-transform solution, and the sound-speed ratio sqrt(gamma) between
+the energy-conserving and the isothermal model."""
+import numpy as np
+import pytest
+from scipy import optimize
+
+from oracle import analysis as an
+from paper_1909_08406_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    from paper_1909_08406_amd import lbm
+    return lbm
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def test_isothermal_init_matches_oracle(L, orc):
+    dims = (9, 5, 4)
+    F = wl.random_state(*dims, seed=21, amp_u=0.2, amp_rho=0.05)
+    _, _, th = L.lattice()
+    ctx = L.init([(*dims, 0.6)], *F.absolute(th), storage="f64", isothermal=True)
+    assert ctx.info()["flags"] & L.FLAG_ISOTHERMAL
+    got = ctx.get_populations().reshape(41, -1)
+    ctx.free()
+    ref = orc.init(*dims, *F.absolute(th), model="isothermal")
+    assert np.max(np.abs(got - ref)) < 2e-15
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_isothermal_random_state_vs_oracle(L, orc, storage, tol):
+    """Ragged 13x7x5 box from a random state, 12 steps, against the oracle's
+    isothermal run: the GPU's held (post-collision) populations against the
+    oracle's collision of its state, and the conserved moments rho, j
+    (normwise, 1e-12 FP64, 1e-5 FP32). This model does not conserve energy,
+    so the post-collision E is not the oracle's pre-collision E."""
+    dims, tau, steps = (13, 7, 5), 0.58, 12
+    F = wl.random_state(*dims, seed=22, amp_u=0.1, amp_rho=0.02, amp_theta=0.02)
+    _, _, th = L.lattice()
+    ctx = L.init([(*dims, tau)], *F.absolute(th), storage=storage, isothermal=True)
+    ctx.step(steps)
+    m = ctx.moments()
+    g = ctx.get_populations().reshape(41, -1)
+    assert ctx.status() == 0
+    ctx.free()
+    f = orc.run(*dims, 1 / tau, orc.init(*dims, *F.absolute(th), model="isothermal"), steps, model="isothermal")
+    m_ref = orc.moment_fields(f)
+    err = float(np.max(np.abs(m[:4] - m_ref[:4])) / np.max(np.abs(m_ref[:4])))
+    gref = orc.collide_field(*dims, 1 / tau, f, model="isothermal")
+    perr = float(np.max(np.abs(g - gref)) / np.max(np.abs(gref)))
+    say("isothermal %s: moment error %.2e, population error %.2e" % (storage, err, perr))
+    assert err <= tol and perr <= 10 * tol
+
+
+@pytest.mark.parametrize("storage,sr", [("f32", False), ("f16s", True)])
+def test_isothermal_batched_and_graph_identical_to_per_box(L, storage, sr):
+    boxes = [(5, 3, 7, 0.6), (16, 8, 4, 0.55), (1, 2, 1, 0.9)]
+    cat = wl.concat([wl.random_state(b[0], b[1], b[2], seed=60 + i, amp_u=0.03, amp_rho=1e-3)
+                     for i, b in enumerate(boxes)])
+    _, _, th = L.lattice()
+    out = []
+    for tuning in (dict(schedule="per_box"), dict(schedule="batched", graph_steps=4)):
+        ctx = L.init(boxes, cat[0], cat[1], cat[2], cat[3], cat[4] * th, storage=storage, stochastic=sr,
+                     isothermal=True)
+        ctx.set_tuning(**tuning)
+        ctx.step(9)
+        out.append(ctx.get_populations())
+        ctx.free()
+    assert np.array_equal(out[0], out[1])
+
+
+def _fit_damped_cosine(t, sig, w0, g0):
+    r = optimize.least_squares(lambda p: p[0] * np.exp(-p[1] * t) * np.cos(p[2] * t + p[3]) - sig,
+                               [1.0, g0, w0, 0.0], x_scale=[1.0, g0, w0, 1.0], xtol=1e-15, ftol=1e-15, gtol=1e-15)
+    return r.x[2], r.x[1]
+
+
+@pytest.mark.parametrize("storage,sr", [("f64", False), ("f32", True), ("f16s", True)])
+def test_sound_speed_ratio_is_sqrt_gamma(L, storage, sr):
+    """Standing wave 64x4x4, amplitude 1e-3, tau 0.6, 400 steps, with both
+    models: isothermal sound speed sqrt(theta0) and damping nu k^2, thermal
+    sound speed sqrt(gamma theta0), each within 0.1% (damping 1%), and their
+    ratio sqrt(5/3) within 0.1% (Sec. VI)."""
+    nx, ny, nz, tau, steps = 64, 4, 4, 0.6, 400
+    k = 2 * np.pi / nx
+    _, _, th = L.lattice()
+    nu = an.viscosity(th, tau)
+    F = wl.standing_wave(nx, ny, nz, 1e-3)
+    speeds = {}
+    for iso in (False, True):
+        ctx = L.init([(nx, ny, nz, tau)], *F.absolute(th), storage=storage, stochastic=sr, isothermal=iso)
+        t, a = [], []
+        for s in range(0, steps + 1, 2):
+            if s:
+                ctx.step(2)
+            t.append(s)
+            a.append(ctx.project(0, (k, 0, 0))[0])
+        ctx.free()
+        t, sig = np.array(t, float), -2 * np.array(a).imag / 1e-3
+        keep = t >= 10
+        if iso:
+            w, g = _fit_damped_cosine(t[keep], sig[keep], np.sqrt(th) * k, nu * k * k)
+            assert abs(g / (nu * k * k) - 1) < 1e-2, g
+        else:
+            ac, _ = an.nsf_modes(k, nu, nu, th)
+            w = an.fit_acoustic_entropy(t[keep], sig[keep], ac.imag, -ac.real)["w"]
+        speeds[iso] = w / k
+    ratio = speeds[False] / speeds[True]
+    say("%s%s: thermal c_s/sqrt(gamma theta0)-1 = %.2e, isothermal c_s/sqrt(theta0)-1 = %.2e, "
+        "ratio/sqrt(5/3)-1 = %.2e" % (storage, "+SR" if sr else "", speeds[False] / np.sqrt(an.GAMMA * th) - 1,
+                                      speeds[True] / np.sqrt(th) - 1, ratio / np.sqrt(an.GAMMA) - 1))
+    assert abs(speeds[False] / np.sqrt(an.GAMMA * th) - 1) < 1e-3
+    assert abs(speeds[True] / np.sqrt(th) - 1) < 1e-3
+    assert abs(ratio / np.sqrt(an.GAMMA) - 1) < 1e-3
+
+
+def _centerline(m, n):
+    idx = np.arange(n) + (n // 2) * n
+    rho = m[0][idx]
+    th = an.temperature(rho, m[1][idx], m[2][idx], m[3][idx], m[4][idx])
+    return rho, rho * th, np.abs(np.arange(n) - n / 2)
+
+
+@pytest.mark.parametrize("storage,sr", [("f32", True), ("f16s", True)])
+def test_paper_2d_pulse(L, storage, sr):
+    """The paper's 2D acoustic pulse (Sec. VI): 800x800 cells, one cell (two
+    node layers) in z, periodic; eps 1e-3, half width b = 40 cells (the
+    paper's b = 0.1 on [-1, 1]); tau 0.51. Isothermal density along the
+    centreline at t = 160 and 284 against the Hankel solution with sound
+    speed sqrt(theta0) and damping nu k^2 (within 5e-3 of eps), and the
+    thermal pressure fluctuation at t* = 124, 220 against the isothermal one
+    at sqrt(gamma) t* = 160.08, 284.02 ~ 160, 284 (within 1e-2 of theta0 eps).
+    The pulse stays inside the periodic box (front plus three half widths
+    below 400 cells from the centre)."""
+    n, b, tau, eps = 800, 40.0, 0.51, 1e-3
+    _, _, th = L.lattice()
+    nu = an.viscosity(th, tau)
+    F = wl.gaussian_pulse_2d(n, n, 1, eps=eps, b=b)
+    iso_lines, th_lines = {}, {}
+    for iso, times in ((True, (160, 284)), (False, (124, 220))):
+        ctx = L.init([(n, n, 1, tau)], *F.absolute(th), storage=storage, stochastic=sr, isothermal=iso)
+        done = 0
+        for t in times:
+            ctx.step(t - done)
+            done = t
+            rho, p, r = _centerline(ctx.moments(), n)
+            (iso_lines if iso else th_lines)[t] = (rho, p, r)
+        assert ctx.status() == 0
+        ctx.free()
+    for t in (160, 284):
+        rho, _, r = iso_lines[t]
+        ref = an.pulse_2d(r, t, eps, b, np.sqrt(th), nu_eff=nu)
+        err = float(np.max(np.abs(rho - 1 - ref)) / eps)
+        say("2D pulse %s%s isothermal t=%d: max |rho' - solution| / eps = %.2e" % (storage, "+SR" if sr else "", t, err))
+        assert err < 5e-3
+    for t, ti in ((124, 160), (220, 284)):
+        err = float(np.max(np.abs(th_lines[t][1] - iso_lines[ti][1])) / (th * eps))
+        say("2D pulse %s%s: thermal p'(t=%d) vs isothermal p'(t=%d): %.2e of theta0 eps" % (storage, "+SR" if sr else "",
+                                                                                         t, ti, err))
+        assert err < 1e-2

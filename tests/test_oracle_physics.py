@@ -290,3 +290,52 @@ def test_sound_speed_ratio_is_sqrt_gamma(orc):
     assert abs(speeds["thermal"] / np.sqrt(an.GAMMA * th) - 1) < 1e-3
     assert abs(speeds["isothermal"] / np.sqrt(th) - 1) < 1e-3
     assert abs(speeds["thermal"] / speeds["isothermal"] / np.sqrt(an.GAMMA) - 1) < 1e-3
+
+
+def _centerline(m, n):
+    """rho, p' = rho theta - theta0 (theta0 added back by the caller) and x
+    positions of the sublattice-0 row through the pulse centre."""
+    idx = np.arange(n) + (n // 2) * n
+    rho = m[0][idx]
+    th = an.temperature(rho, m[1][idx], m[2][idx], m[3][idx], m[4][idx])
+    return rho, rho * th, np.abs(np.arange(n) - n / 2)
+
+
+def test_pulse_2d_solution_at_t0_is_the_gaussian():
+    r = np.linspace(0, 40, 41)
+    g = an.pulse_2d(r, 0.0, 1e-3, 6.0, 0.5)
+    assert np.max(np.abs(g - 1e-3 * np.exp(-np.log(2.0) / 36.0 * r * r))) < 1e-15
+
+
+def test_pulse_2d_oracle_runs_match_bessel_solution(orc):
+    """The paper's 2D pulse (Sec. VI) at small size: 96x96 cells, one cell
+    (two node layers) in z, eps 1e-3, b = 6, tau 0.55, 40 steps. Isothermal
+    density and thermal pressure along the centreline against the Hankel
+    solution with sound speeds sqrt(theta0) and sqrt(gamma theta0) and their
+    acoustic damping (nu k^2; the NSF attenuation), within 5e-3 of eps."""
+    c, w, th = _lattice(orc)
+    n, b, tau, eps, T = 96, 6.0, 0.55, 1e-3, 40
+    F = wl.gaussian_pulse_2d(n, n, 1, eps=eps, b=b)
+    nu = an.viscosity(th, tau)
+    f = orc.run(n, n, 1, 1 / tau, orc.init(n, n, 1, *F.absolute(th), model="isothermal"), T, model="isothermal")
+    rho, _, r = _centerline(orc.moment_fields(f), n)
+    ref = an.pulse_2d(r, T, eps, b, np.sqrt(th), nu_eff=nu)
+    assert np.max(np.abs(rho - 1 - ref)) < 5e-3 * eps
+    f = orc.run(n, n, 1, 1 / tau, orc.init(n, n, 1, *F.absolute(th)), T)
+    _, p, r = _centerline(orc.moment_fields(f), n)
+    ac, _ = an.nsf_modes(0.05, nu, nu, th)
+    ref = th * an.pulse_2d(r, T, eps, b, np.sqrt(an.GAMMA * th), nu_eff=-ac.real / 0.05 ** 2)
+    assert np.max(np.abs(p - th - ref)) < 5e-3 * th * eps
+
+
+def test_pulse_2d_thermal_at_t_equals_isothermal_at_sqrt_gamma_t(orc):
+    """The paper's comparison (Sec. VI): the thermal pressure fluctuation at
+    t* against the isothermal one at sqrt(gamma) t* (t* = 31, 40.02 ~ 40)."""
+    c, w, th = _lattice(orc)
+    n, b, tau, eps = 96, 6.0, 0.55, 1e-3
+    F = wl.gaussian_pulse_2d(n, n, 1, eps=eps, b=b)
+    f = orc.run(n, n, 1, 1 / tau, orc.init(n, n, 1, *F.absolute(th)), 31)
+    _, p_th, _ = _centerline(orc.moment_fields(f), n)
+    f = orc.run(n, n, 1, 1 / tau, orc.init(n, n, 1, *F.absolute(th), model="isothermal"), 40, model="isothermal")
+    _, p_iso, _ = _centerline(orc.moment_fields(f), n)
+    assert np.max(np.abs(p_th - p_iso)) < 1e-2 * th * eps
