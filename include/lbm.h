@@ -155,6 +155,17 @@ int lbm_init(lbm_ctx **out, const lbm_box *boxes, int32_t nboxes, const lbm_opts
              const double *theta, void *stream, void *workspace, uint64_t workspace_bytes);
 
 /*
+ * As lbm_init, with the five field arrays in device memory (FP64, all boxes
+ * concatenated, the same layout): the equilibrium is built from them in
+ * place, with no host copy. The caller keeps them alive until the call
+ * returns. Unrealisable values (rho <= 0, theta <= 0, non-finite) are found
+ * on the device and reported as LBM_E_DOMAIN. Errors as lbm_init.
+ */
+int lbm_init_device(lbm_ctx **out, const lbm_box *boxes, int32_t nboxes, const lbm_opts *opts,
+                    const double *rho, const double *ux, const double *uy, const double *uz,
+                    const double *theta, void *stream, void *workspace, uint64_t workspace_bytes);
+
+/*
  * n >= 0 fused collide-and-stream steps of every box (Sec. II), queued on
  * the context stream without a host synchronisation. A step is one launch
  * per box or one launch over all boxes, optionally replayed from captured

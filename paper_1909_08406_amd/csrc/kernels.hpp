@@ -344,16 +344,29 @@ __device__ inline void block_max_float(float v, float* out)
     }
 }
 
+// Nodal FP64 fields of one chunk of nodes (host data staged on the device,
+// or device arrays of the caller), element i for node n0 + i.
+struct InitFields {
+    const double* rho;
+    const double* ux;
+    const double* uy;
+    const double* uz;
+    const double* th;
+};
+
 template <class ST>
 __global__ __launch_bounds__(BLOCK) void k_init(typename ST::T* __restrict__ f, uint32_t N, uint32_t n0,
-                                                uint32_t count, const double* __restrict__ fields, StepParams p,
-                                                int mode, float* maxdev)
+                                                uint32_t count, InitFields fields, StepParams p, int mode,
+                                                float* maxdev)
 {
     const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
     float dev = 0.f;
     if (i < count) {
-        const double rho = fields[i], ux = fields[count + i], uy = fields[2 * count + i],
-                     uz = fields[3 * count + i], th = fields[4 * count + i];
+        const double rho = fields.rho[i], ux = fields.ux[i], uy = fields.uy[i], uz = fields.uz[i], th = fields.th[i];
+        // the domain: rho > 0, theta > 0 (checked but unused by the
+        // isothermal model), all finite
+        const bool in_domain = rho > 0.0 && th > 0.0 && fabs(rho) < 1e300 && fabs(th) < 1e300 &&
+                               fabs(ux) < 1e300 && fabs(uy) < 1e300 && fabs(uz) < 1e300;
         // storage reference: rho0 for the shifted forms, the weights themselves otherwise
         const double rref = ST::shifted ? p.rho_ref : 1.0;
         double D[Q];
@@ -373,7 +386,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(typename ST::T* __restrict__ f, 
                 ST::store(f + size_t(q) * N + n0 + i, typename ST::R(v));
             }
         });
-        if (bad) atomicOr(p.flag, 1u);
+        if (bad || !in_domain) atomicOr(p.flag, 1u);
     }
     if (mode == 0) block_max_float(dev, maxdev);
 }

@@ -354,30 +354,41 @@ int graph_for(lbm_ctx* ctx, hipGraphExec_t* out)
     return LBM_OK;
 }
 
-// Copy nodal FP64 fields of box b chunk by chunk and run the init kernel.
-int run_init(lbm_ctx* ctx, const BoxDev& b, uint64_t node_base, const double* const fields[5], int mode,
-             float* maxdev)
+// Run the init kernel over box b chunk by chunk. Host fields are copied
+// through the staging area; device fields (device_fields) are read in place.
+int run_init(lbm_ctx* ctx, const BoxDev& b, uint64_t node_base, const double* const fields[5], bool device_fields,
+             int mode, float* maxdev)
 {
-    const uint64_t chunk = ctx->L.staging_bytes / (5 * sizeof(double));
+    const uint64_t chunk = device_fields ? uint64_t(1) << 30 : ctx->L.staging_bytes / (5 * sizeof(double));
     double* stage = reinterpret_cast<double*>(ctx->staging);
     for (uint64_t n0 = 0; n0 < b.nodes; n0 += chunk) {
         const uint64_t cnt = std::min(chunk, b.nodes - n0);
-        for (int k = 0; k < 5; ++k)
-            HIPCHK(hipMemcpyAsync(stage + k * cnt, fields[k] + node_base + n0, cnt * sizeof(double),
-                                  hipMemcpyHostToDevice, ctx->stream));
+        InitFields in;
+        const double** dst[5] = {&in.rho, &in.ux, &in.uy, &in.uz, &in.th};
+        for (int k = 0; k < 5; ++k) {
+            if (device_fields) {
+                *dst[k] = fields[k] + node_base + n0;
+            } else {
+                HIPCHK(hipMemcpyAsync(stage + k * cnt, fields[k] + node_base + n0, cnt * sizeof(double),
+                                      hipMemcpyHostToDevice, ctx->stream));
+                *dst[k] = stage + k * cnt;
+            }
+        }
         const StepParams p = ctx->params(b);
         int rc = dispatch_storage(ctx->storage, [&](auto st) {
             using ST = decltype(st);
             using T = typename ST::T;
             T* f = reinterpret_cast<T*>(ctx->buf(ctx->cur)) + b.offset;
             hipLaunchKernelGGL((k_init<ST>), dim3(nblocks(cnt)), dim3(BLOCK), 0, ctx->stream, f, uint32_t(b.nodes),
-                               uint32_t(n0), uint32_t(cnt), stage, p, mode, maxdev);
+                               uint32_t(n0), uint32_t(cnt), in, p, mode, maxdev);
             return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
         });
         if (rc) return rc;
         // the staging area is reused by the next chunk
-        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (!device_fields) HIPCHK(hipStreamSynchronize(ctx->stream));
     }
+    // the caller reads the flag and the measured deviation next
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     return LBM_OK;
 }
 
@@ -437,9 +448,9 @@ int lbm_workspace_size(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opt
     return LBM_OK;
 }
 
-int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts, const double* rho,
-             const double* ux, const double* uy, const double* uz, const double* theta, void* stream,
-             void* workspace, uint64_t workspace_bytes)
+static int init_impl(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts, const double* rho,
+                     const double* ux, const double* uy, const double* uz, const double* theta, bool device_fields,
+                     void* stream, void* workspace, uint64_t workspace_bytes)
 {
     if (!out) return LBM_E_ARG;
     *out = nullptr;
@@ -470,8 +481,9 @@ int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts
         ctx->boxes.push_back(d);
     }
 
-    // domain check of the input fields (host side, before any device work)
-    const uint64_t total = ctx->L.elems / Q;
+    // domain check of host fields before any device work (device fields are
+    // checked by the init kernel, which raises the flag read below)
+    const uint64_t total = device_fields ? 0 : ctx->L.elems / Q;
     for (uint64_t i = 0; i < total; ++i) {
         if (!(rho[i] > 0.0) || !(theta[i] > 0.0) || !std::isfinite(rho[i]) || !std::isfinite(theta[i]) ||
             !std::isfinite(ux[i]) || !std::isfinite(uy[i]) || !std::isfinite(uz[i])) {
@@ -536,7 +548,7 @@ int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts
             if (hipMemsetAsync(maxdev, 0, sizeof(float), ctx->stream) != hipSuccess) return fail(LBM_E_HIP);
             uint64_t base = 0;
             for (const BoxDev& b : ctx->boxes) {
-                rc = run_init(ctx, b, base, fields, 0, maxdev);
+                rc = run_init(ctx, b, base, fields, device_fields, 0, maxdev);
                 if (rc) return fail(rc);
                 base += b.nodes;
             }
@@ -553,7 +565,7 @@ int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts
 
     uint64_t base = 0;
     for (const BoxDev& b : ctx->boxes) {
-        rc = run_init(ctx, b, base, fields, 1, nullptr);
+        rc = run_init(ctx, b, base, fields, device_fields, 1, nullptr);
         if (rc) return fail(rc);
         base += b.nodes;
     }
@@ -564,6 +576,20 @@ int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts
     if (rc) return fail(rc);
     *out = ctx;
     return LBM_OK;
+}
+
+int lbm_init(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts, const double* rho,
+             const double* ux, const double* uy, const double* uz, const double* theta, void* stream,
+             void* workspace, uint64_t workspace_bytes)
+{
+    return init_impl(out, boxes, nboxes, opts, rho, ux, uy, uz, theta, false, stream, workspace, workspace_bytes);
+}
+
+int lbm_init_device(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts, const double* rho,
+                    const double* ux, const double* uy, const double* uz, const double* theta, void* stream,
+                    void* workspace, uint64_t workspace_bytes)
+{
+    return init_impl(out, boxes, nboxes, opts, rho, ux, uy, uz, theta, true, stream, workspace, workspace_bytes);
 }
 
 int lbm_step(lbm_ctx* ctx, int32_t n)

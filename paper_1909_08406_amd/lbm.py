@@ -70,6 +70,8 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_uint64)]),
     "lbm_init": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(Box), ctypes.c_int32, ctypes.POINTER(Opts),
                                 _dp, _dp, _dp, _dp, _dp, _vp, _vp, ctypes.c_uint64]),
+    "lbm_init_device": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(Box), ctypes.c_int32, ctypes.POINTER(Opts),
+                                       _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint64]),
     "lbm_step": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "lbm_synchronize": (ctypes.c_int, [_vp]),
     "lbm_moments": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
@@ -316,6 +318,34 @@ def init(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0
     rc = lib().lbm_init(ctypes.byref(h), bx, len(boxes), ctypes.byref(op), *[_d(a) for a in arrs], sptr,
                         ws_ptr, ws_bytes)
     _check(rc, "lbm_init")
+    return Context(h, boxes, ws, stream)
+
+
+def init_device(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0, newton_iters=0,
+                shift_exp=None, stream=None, stochastic=False, seed=0, isothermal=False):
+    """lbm_init_device: the five fields are contiguous float64 torch CUDA
+    tensors (all boxes concatenated); the equilibrium is built from them on
+    the device. The workspace is a torch uint8 tensor held by the Context."""
+    import torch
+    bx = _boxes(boxes)
+    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, seed, isothermal)
+    nodes = sum(2 * b[0] * b[1] * b[2] for b in boxes)
+    fields = (rho, ux, uy, uz, theta)
+    for a in fields:
+        if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()):
+            raise TypeError("init_device takes contiguous float64 CUDA tensors")
+        if a.numel() != nodes:
+            raise ValueError("field has %d values, boxes have %d nodes" % (a.numel(), nodes))
+    ws_bytes = workspace_size(boxes, storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, isothermal)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    sptr = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    if stream is not None:
+        # the fields were written on torch's current stream
+        stream.wait_stream(torch.cuda.current_stream())
+    h = _vp()
+    rc = lib().lbm_init_device(ctypes.byref(h), bx, len(boxes), ctypes.byref(op), *[a.data_ptr() for a in fields],
+                               sptr, ws.data_ptr(), ws_bytes)
+    _check(rc, "lbm_init_device")
     return Context(h, boxes, ws, stream)
 
 

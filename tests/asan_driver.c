@@ -1,0 +1,120 @@
+/* Host-only exercise of the C-ABI (test helper): every entry point that
+ * needs no device, with valid and invalid arguments, for a build of the
+ * library whose host code carries AddressSanitizer. Prints "ok" and exits 0
+ * when every return code is the documented one. */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "lbm.h"
+
+static int fails = 0;
+#define EXPECT(cond)                                                   \
+    do {                                                               \
+        if (!(cond)) {                                                 \
+            fprintf(stderr, "line %d: %s\n", __LINE__, #cond);         \
+            ++fails;                                                   \
+        }                                                              \
+    } while (0)
+
+int main(void)
+{
+    double c[41 * 3], w[41], t0 = 0.0;
+    EXPECT(lbm_lattice(c, w, &t0) == LBM_OK);
+    EXPECT(lbm_lattice(NULL, NULL, NULL) == LBM_OK);
+    EXPECT(t0 > 0.29 && t0 < 0.3);
+    EXPECT(lbm_selftest() == LBM_OK);
+
+    lbm_box box = {5, 3, 2, 0, 0.6};
+    lbm_opts opts;
+    memset(&opts, 0, sizeof(opts));
+    opts.storage = LBM_F32;
+    opts.tau_conv = LBM_TAU_LB;
+    opts.rho0 = 1.0;
+    opts.shift_exp = LBM_SHIFT_AUTO;
+    uint64_t bytes = 0;
+    EXPECT(lbm_workspace_size(&box, 1, &opts, &bytes) == LBM_OK && bytes > 0);
+    EXPECT(lbm_workspace_size(&box, 1, &opts, NULL) == LBM_E_ARG);
+    EXPECT(lbm_workspace_size(NULL, 1, &opts, &bytes) == LBM_E_ARG);
+    EXPECT(lbm_workspace_size(&box, 0, &opts, &bytes) == LBM_E_ARG);
+    lbm_box bad = box;
+    bad.tau = 0.5;
+    EXPECT(lbm_workspace_size(&bad, 1, &opts, &bytes) == LBM_E_ARG);
+    bad = box;
+    bad.nx = 0;
+    EXPECT(lbm_workspace_size(&bad, 1, &opts, &bytes) == LBM_E_ARG);
+    lbm_opts o2 = opts;
+    o2.storage = (lbm_storage)9;
+    EXPECT(lbm_workspace_size(&box, 1, &o2, &bytes) == LBM_E_ARG);
+    o2 = opts;
+    o2.flags = 0x80u;
+    EXPECT(lbm_workspace_size(&box, 1, &o2, &bytes) == LBM_E_ARG);
+
+    /* host collision of a perturbed rest state, both models and precisions */
+    double f[41], g[41];
+    for (int q = 0; q < 41; ++q) f[q] = w[q] * (1.0 + 1e-3 * sin(1.0 + q));
+    for (int pr = 0; pr < 2; ++pr)
+        for (uint32_t fl = 0; fl <= LBM_FLAG_ISOTHERMAL; fl += LBM_FLAG_ISOTHERMAL) {
+            EXPECT(lbm_collide_host(pr, pr ? 1 : 3, fl, 1.0 / 0.6, f, g) == LBM_OK);
+            double m0 = 0.0, m1 = 0.0;
+            for (int q = 0; q < 41; ++q) {
+                m0 += f[q];
+                m1 += g[q];
+            }
+            EXPECT(fabs(m1 - m0) < 1e-6);
+        }
+    EXPECT(lbm_collide_host(2, 1, 0, 1.0, f, g) == LBM_E_ARG);
+    EXPECT(lbm_collide_host(0, 9, 0, 1.0, f, g) == LBM_E_ARG);
+    EXPECT(lbm_collide_host(0, 1, 0x10u, 1.0, f, g) == LBM_E_ARG);
+    EXPECT(lbm_collide_host(0, 1, 0, 1.0, NULL, g) == LBM_E_ARG);
+
+    int32_t blk = 0;
+    uint32_t flags = 0;
+    EXPECT(lbm_num_variants() > 0);
+    EXPECT(lbm_variant_desc(0, &blk, &flags) == LBM_OK && blk > 0);
+    EXPECT(lbm_variant_desc(-1, &blk, &flags) == LBM_E_ARG);
+    EXPECT(lbm_variant_desc(lbm_num_variants(), &blk, &flags) == LBM_E_ARG);
+    for (int code = 1; code >= -8; --code) EXPECT(lbm_strerror(code) != NULL && strlen(lbm_strerror(code)) > 0);
+
+    /* lbm_init: argument and domain errors are found before device work */
+    const int n = 2 * 5 * 3 * 2;
+    double *rho = malloc(sizeof(double) * n), *ux = calloc(n, sizeof(double)), *uy = calloc(n, sizeof(double)),
+           *uz = calloc(n, sizeof(double)), *th = malloc(sizeof(double) * n);
+    for (int i = 0; i < n; ++i) {
+        rho[i] = 1.0;
+        th[i] = t0;
+    }
+    lbm_ctx *ctx = (lbm_ctx *)0x1;
+    EXPECT(lbm_init(NULL, &box, 1, &opts, rho, ux, uy, uz, th, NULL, NULL, 0) == LBM_E_ARG);
+    EXPECT(lbm_init(&ctx, &box, 1, &opts, NULL, ux, uy, uz, th, NULL, NULL, 0) == LBM_E_ARG && ctx == NULL);
+    EXPECT(lbm_init(&ctx, &box, 0, &opts, rho, ux, uy, uz, th, NULL, NULL, 0) == LBM_E_ARG);
+    rho[n - 1] = -1.0;
+    EXPECT(lbm_init(&ctx, &box, 1, &opts, rho, ux, uy, uz, th, NULL, NULL, 0) == LBM_E_DOMAIN && ctx == NULL);
+    rho[n - 1] = 1.0;
+    th[3] = NAN;
+    EXPECT(lbm_init(&ctx, &box, 1, &opts, rho, ux, uy, uz, th, NULL, NULL, 0) == LBM_E_DOMAIN);
+    EXPECT(lbm_init_device(NULL, &box, 1, &opts, rho, ux, uy, uz, th, NULL, NULL, 0) == LBM_E_ARG);
+    free(rho);
+    free(ux);
+    free(uy);
+    free(uz);
+    free(th);
+
+    /* NULL contexts */
+    lbm_info info;
+    lbm_tuning tun;
+    double out5[5];
+    EXPECT(lbm_step(NULL, 1) == LBM_E_ARG);
+    EXPECT(lbm_get_info(NULL, &info) == LBM_E_ARG);
+    EXPECT(lbm_get_tuning(NULL, &tun) == LBM_E_ARG);
+    EXPECT(lbm_totals(NULL, out5) == LBM_E_ARG);
+    EXPECT(lbm_status(NULL) == LBM_E_ARG);
+    EXPECT(lbm_stream(NULL) == NULL);
+    lbm_free(NULL);
+
+    if (fails) return 1;
+    printf("ok\n");
+    return 0;
+}

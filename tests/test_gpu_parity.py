@@ -365,3 +365,65 @@ def test_autotune_keeps_state(L):
     assert np.array_equal(ctx.get_populations(), ref.get_populations())
     ctx.free()
     ref.free()
+
+
+INIT_FORMS = [("f64", False, False), ("f32", False, False), ("f16s", True, False), ("bf16s", True, False),
+              ("f32", False, True)]
+
+
+@pytest.mark.parametrize("storage,sr,iso", INIT_FORMS)
+def test_init_device_identical_to_host_init(L, storage, sr, iso):
+    """lbm_init_device (fields in device memory, no host staging) builds the
+    same populations and the same shift exponent as lbm_init, and the runs
+    stay identical."""
+    import torch
+    boxes = [(9, 5, 3, 0.6), (16, 4, 2, 0.7), (1, 1, 1, 0.55)]
+    cat = wl.concat([wl.random_state(b[0], b[1], b[2], seed=80 + i, amp_u=0.05, amp_rho=2e-3, amp_theta=2e-3)
+                     for i, b in enumerate(boxes)])
+    _, _, th = L.lattice()
+    host = L.init(boxes, cat[0], cat[1], cat[2], cat[3], cat[4] * th, storage=storage, stochastic=sr, isothermal=iso)
+    dev_fields = [torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+                  for a in (cat[0], cat[1], cat[2], cat[3], cat[4] * th)]
+    dev = L.init_device(boxes, *dev_fields, storage=storage, stochastic=sr, isothermal=iso)
+    assert dev.info()["shift_exp"] == host.info()["shift_exp"]
+    assert np.array_equal(dev.get_populations(), host.get_populations())
+    host.step(5)
+    dev.step(5)
+    assert np.array_equal(dev.get_populations(), host.get_populations())
+    host.free()
+    dev.free()
+
+
+def test_init_device_rejects_unrealisable_fields(L):
+    import torch
+    dims = (6, 4, 3)
+    F = wl.random_state(*dims, seed=3, amp_u=0.02)
+    _, _, th = L.lattice()
+    base = [np.array(a, dtype=np.float64) for a in F.absolute(th)]
+    for k, i, bad in [(0, 5, 0.0), (0, 7, -1.0), (4, 11, -0.1), (1, 3, np.nan), (3, 0, np.inf)]:
+        arrs = [a.copy() for a in base]
+        arrs[k][i] = bad
+        t = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in arrs]
+        with pytest.raises(L.LbmError) as e:
+            L.init_device([(*dims, 0.6)], *t, storage="f32")
+        assert e.value.code == L.E_DOMAIN, (k, i, bad)
+
+
+def test_workspace_too_small_is_nomem(L):
+    """A caller workspace below lbm_workspace_size is refused with
+    LBM_E_NOMEM before any device work."""
+    import ctypes
+    import torch
+    dims = (8, 4, 4)
+    F = wl.random_state(*dims, seed=4, amp_u=0.02)
+    _, _, th = L.lattice()
+    boxes = [(*dims, 0.6)]
+    need = L.workspace_size(boxes, "f32")
+    ws = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in F.absolute(th)]
+    h = ctypes.c_void_p()
+    op = L._opts("f32", L.TAU_LB, 1.0, 0, None)
+    rc = L.lib().lbm_init(ctypes.byref(h), L._boxes(boxes), 1, ctypes.byref(op),
+                          *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs], None,
+                          ws.data_ptr(), need - 256)
+    assert rc == L.E_NOMEM and not h.value

@@ -1,0 +1,42 @@
+"""The C-ABI's host code under AddressSanitizer: the library is built with
+the sanitizer on its host code only (device code unoptimised) and a C
+driver (asan_driver.c) calls every entry point that needs no device, with
+valid and invalid arguments. Any out-of-bounds access, use after free or
+leak in that host code fails the run."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HIPCC = os.path.join(ROCM, "bin", "hipcc")
+CLANG = os.path.join(ROCM, "llvm", "bin", "clang")
+
+
+@pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)), reason="ROCm toolchain not found")
+def test_host_code_is_clean_under_address_sanitizer(tmp_path):
+    so = tmp_path / "liblbm_host_asan.so"
+    src = os.path.join(ROOT, "paper_1909_08406_amd", "csrc", "lbm.hip")
+    inc = os.path.join(ROOT, "include")
+    # device code unoptimised (it is not exercised here); the sanitizer is
+    # applied to the host code alone
+    build = [HIPCC, "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-O1", "-g",
+             "-std=c++17", "-fPIC", "-shared", "-fno-omit-frame-pointer", "-Xarch_device", "-O0",
+             "-Xarch_host", "-fsanitize=address", "-I", inc, "-o", str(so), src]
+    r = subprocess.run(build, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    exe = tmp_path / "asan_driver"
+    link = [CLANG, "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer", "-I", inc,
+            os.path.join(ROOT, "tests", "asan_driver.c"), str(so), "-Wl,-rpath," + str(tmp_path),
+            "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-lm", "-o", str(exe)]
+    r = subprocess.run(link, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    env = dict(os.environ)
+    # leaks inside the HIP runtime's own start-up are not this library's;
+    # reports are kept for allocations made from the library's code
+    env["ASAN_OPTIONS"] = "detect_leaks=1:abort_on_error=0:exitcode=23"
+    env["LSAN_OPTIONS"] = "suppressions=" + os.path.join(ROOT, "tests", "asan_runtime.supp")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=120)
+    assert r.returncode == 0 and "ok" in r.stdout, (r.returncode, r.stdout[-2000:], r.stderr[-4000:])
