@@ -78,7 +78,9 @@ typedef enum {
                                            the mass and momentum constraints only, i.e. no c^2
                                            multiplier and temperature theta0; sound speed
                                            sqrt(theta0). The theta field of lbm_init is
-                                           checked but not used. */
+                                           checked but not used. Steps run the default
+                                           launch shape (256 threads, no hints);
+                                           lbm_tuning.variant is not used. */
 
 /* Meaning of lbm_box.tau. */
 typedef enum {

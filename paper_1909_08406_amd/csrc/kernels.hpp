@@ -47,10 +47,11 @@ struct CollideConst {
     R rho_ref;       // rho0 (shifted storage) or 1
     R inv_scale[6];  // 2^{-k_s} (shifted) or 1
     R omw[6];        // omega w_s rho_ref 2^{k_s} (shifted) or omega w_s
-    bool iso;        // isothermal equilibrium (mass and momentum only)
 };
 
-template <typename R, bool SHIFTED, int NEWTON>
+// ISO: the isothermal equilibrium (mass and momentum only) instead of the
+// energy-conserving one.
+template <typename R, bool SHIFTED, int NEWTON, bool ISO = false>
 __host__ __device__ inline void collide(const R x[Q], R y[Q], const CollideConst<R>& cc, R& rho_out, R& theta_out)
 {
     ShellSums<R> SS;
@@ -92,7 +93,7 @@ __host__ __device__ inline void collide(const R x[Q], R y[Q], const CollideConst
     theta_out = theta;
 
     Mult<R> m;
-    if (cc.iso) {
+    if constexpr (ISO) {
         // isothermal: g = 0, Maxwellian guess at theta0
         m.b[0] = ux * R(1.0 / THETA0);
         m.b[1] = uy * R(1.0 / THETA0);
@@ -170,7 +171,7 @@ __device__ inline void st_hint(T* p, T v, int nt)
 // storage type in out (round to nearest, or stochastic rounding with bits
 // drawn for node `nid` of the context at the launch's step); raises the
 // flag for an unrealisable node.
-template <class ST, int NEWTON, bool SR>
+template <class ST, int NEWTON, bool SR, bool ISO>
 __device__ inline void collide_encode(const typename ST::R x[Q], typename ST::T out[Q], const StepParams& p,
                                       uint32_t nid)
 {
@@ -178,14 +179,13 @@ __device__ inline void collide_encode(const typename ST::R x[Q], typename ST::T 
     CollideConst<R> cc;
     cc.om = R(p.omega);
     cc.rho_ref = ST::shifted ? R(p.rho_ref) : R(1);
-    cc.iso = p.isothermal != 0;
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
         cc.inv_scale[s] = ST::unit_scale ? R(1) : R(p.inv_scale[s]);
         cc.omw[s] = ST::shifted ? R(p.omw[s]) : cc.om * R(SHELL_W[s]);
     }
     R y[Q], rho, theta;
-    collide<R, ST::shifted, NEWTON>(x, y, cc, rho, theta);
+    collide<R, ST::shifted, NEWTON, ISO>(x, y, cc, rho, theta);
     flag_bad<R>(p, rho, theta);
     uint32_t rs = 0, rw = 0;
     if constexpr (SR) {
@@ -210,7 +210,7 @@ __device__ inline void collide_encode(const typename ST::R x[Q], typename ST::T 
 
 // The step of node n of one box: src and dst are the box's first q-block
 // in the current and the other population buffer.
-template <class ST, int NEWTON, int FL, bool SR>
+template <class ST, int NEWTON, int FL, bool SR, bool ISO>
 __device__ inline void step_node(const char* __restrict__ src, char* __restrict__ dst, const StepParams& p,
                                  uint32_t n)
 {
@@ -228,7 +228,7 @@ __device__ inline void step_node(const char* __restrict__ src, char* __restrict_
                                   FL & FL_NT_LOAD));
     });
     T out[Q];
-    collide_encode<ST, NEWTON, SR>(x, out, p, p.node0 + n);
+    collide_encode<ST, NEWTON, SR, ISO>(x, out, p, p.node0 + n);
     const uint32_t nbytes = n * uint32_t(sizeof(T));
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
@@ -237,14 +237,14 @@ __device__ inline void step_node(const char* __restrict__ src, char* __restrict_
 }
 
 // One box per launch; fin/fout point at the box's first q-block.
-template <class ST, int NEWTON, int BLK, int FL, bool SR>
+template <class ST, int NEWTON, int BLK, int FL, bool SR, bool ISO = false>
 __global__ __launch_bounds__(BLK) void k_step(const typename ST::T* __restrict__ fin,
                                               typename ST::T* __restrict__ fout, StepParams p)
 {
     const uint32_t blk = p.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     const uint32_t n = blk * BLK + threadIdx.x;
     if (n >= p.g.N) return;
-    step_node<ST, NEWTON, FL, SR>(reinterpret_cast<const char*>(fin), reinterpret_cast<char*>(fout), p, n);
+    step_node<ST, NEWTON, FL, SR, ISO>(reinterpret_cast<const char*>(fin), reinterpret_cast<char*>(fout), p, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -259,7 +259,7 @@ struct BatchBox {
     uint64_t offset;  // element offset of the box in a population buffer
 };
 
-template <class ST, int NEWTON, int BLK, int FL, bool SR>
+template <class ST, int NEWTON, int BLK, int FL, bool SR, bool ISO = false>
 __global__ __launch_bounds__(BLK) void k_step_batch(const typename ST::T* __restrict__ fin,
                                                     typename ST::T* __restrict__ fout,
                                                     const BatchBox* __restrict__ boxes,
@@ -274,8 +274,8 @@ __global__ __launch_bounds__(BLK) void k_step_batch(const typename ST::T* __rest
     StepParams p = B.p;
     p.step = step;
     p.step_base = step_base;
-    step_node<ST, NEWTON, FL, SR>(reinterpret_cast<const char*>(fin + B.offset), reinterpret_cast<char*>(fout + B.offset),
-                                  p, n);
+    step_node<ST, NEWTON, FL, SR, ISO>(reinterpret_cast<const char*>(fin + B.offset),
+                                       reinterpret_cast<char*>(fout + B.offset), p, n);
 }
 
 // Device-held step counter read by graph replays (one vector store).

@@ -257,27 +257,34 @@ int enqueue_step(lbm_ctx* ctx, int from, uint32_t step, const uint32_t* step_bas
                                 std::is_same<ST, StoreBF16S>::value;
         return with_newton(ctx->newton, [&](auto nw) {
             constexpr int NEWTON = decltype(nw)::value;
-            auto go = [&](auto sr) {
+            auto launch = [&](auto sr, auto iso, auto blk, auto fl) {
                 constexpr bool SR = decltype(sr)::value;
-                return with_variant(ctx->variant, [&](auto blk, auto fl) {
-                    constexpr int BLK = decltype(blk)::value;
-                    constexpr int FL = decltype(fl)::value;
-                    if (ctx->schedule == LBM_SCHEDULE_BATCHED) {
-                        const int i = blk_index(BLK);
-                        hipLaunchKernelGGL((k_step_batch<ST, NEWTON, BLK, FL, SR>), dim3(uint32_t(ctx->L.ntiles[i])),
-                                           dim3(BLK), 0, s, in, out, ctx->table, ctx->tiles[i], ctx->base.xcd_remap,
-                                           step, step_base);
-                    } else {
-                        for (const BoxDev& b : ctx->boxes) {
-                            StepParams p = ctx->params(b);
-                            p.step = step;
-                            p.step_base = step_base;
-                            hipLaunchKernelGGL((k_step<ST, NEWTON, BLK, FL, SR>),
-                                               dim3(uint32_t((b.nodes + BLK - 1) / BLK)), dim3(BLK), 0, s,
-                                               in + b.offset, out + b.offset, p);
-                        }
+                constexpr bool ISO = decltype(iso)::value;
+                constexpr int BLK = decltype(blk)::value;
+                constexpr int FL = decltype(fl)::value;
+                if (ctx->schedule == LBM_SCHEDULE_BATCHED) {
+                    const int i = blk_index(BLK);
+                    hipLaunchKernelGGL((k_step_batch<ST, NEWTON, BLK, FL, SR, ISO>), dim3(uint32_t(ctx->L.ntiles[i])),
+                                       dim3(BLK), 0, s, in, out, ctx->table, ctx->tiles[i], ctx->base.xcd_remap, step,
+                                       step_base);
+                } else {
+                    for (const BoxDev& b : ctx->boxes) {
+                        StepParams p = ctx->params(b);
+                        p.step = step;
+                        p.step_base = step_base;
+                        hipLaunchKernelGGL((k_step<ST, NEWTON, BLK, FL, SR, ISO>),
+                                           dim3(uint32_t((b.nodes + BLK - 1) / BLK)), dim3(BLK), 0, s,
+                                           in + b.offset, out + b.offset, p);
                     }
-                });
+                }
+            };
+            auto go = [&](auto sr) -> int {
+                if (ctx->base.isothermal) {
+                    // the isothermal model runs the default launch shape
+                    launch(sr, std::true_type{}, std::integral_constant<int, 256>{}, std::integral_constant<int, 0>{});
+                    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+                }
+                return with_variant(ctx->variant, [&](auto blk, auto fl) { launch(sr, std::false_type{}, blk, fl); });
             };
             if constexpr (has_sr) {
                 if (ctx->stochastic) return go(std::true_type{});
@@ -410,14 +417,14 @@ void collide_host(double omega, bool iso, const double* in, double* out)
     CollideConst<R> cc;
     cc.om = R(omega);
     cc.rho_ref = R(1);
-    cc.iso = iso;
     for (int s = 0; s < 6; ++s) {
         cc.inv_scale[s] = R(1);
         cc.omw[s] = cc.om * R(SHELL_W[s]);
     }
     R x[Q], y[Q], rho, theta;
     for (int q = 0; q < Q; ++q) x[q] = R(in[q]);
-    collide<R, false, NEWTON>(x, y, cc, rho, theta);
+    if (iso) collide<R, false, NEWTON, true>(x, y, cc, rho, theta);
+    else collide<R, false, NEWTON, false>(x, y, cc, rho, theta);
     for (int q = 0; q < Q; ++q) out[q] = double(R(x[q] + y[q]));
 }
 }  // namespace
@@ -839,7 +846,7 @@ int lbm_get_info(lbm_ctx* ctx, lbm_info* info)
     info->nboxes = int32_t(ctx->boxes.size());
     info->nodes = int64_t(ctx->L.elems / Q);
     info->bytes_per_step = int64_t(2 * ctx->L.elems * uint64_t(elem_bytes(ctx->storage)));
-    info->block_threads = VARIANTS[ctx->variant].blk;
+    info->block_threads = ctx->base.isothermal ? 256 : VARIANTS[ctx->variant].blk;
     info->variant = ctx->variant;
     info->device_bytes = ctx->L.total;
     return LBM_OK;
