@@ -427,3 +427,58 @@ def test_workspace_too_small_is_nomem(L):
                           *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs], None,
                           ws.data_ptr(), need - 256)
     assert rc == L.E_NOMEM and not h.value
+
+
+_ORACLE_RUNS = {}
+
+
+def cached_oracle_moments(orc, key, dims, tau, F, steps):
+    """Oracle moments of a run, computed once per key for all storage forms."""
+    if key not in _ORACLE_RUNS:
+        _, _, th = orc.lattice()
+        f = orc.run(*dims, 1.0 / tau, orc.init(*dims, *F.absolute(th)), steps)
+        _ORACLE_RUNS[key] = orc.moment_fields(f)
+    return _ORACLE_RUNS[key]
+
+
+@pytest.mark.parametrize("ma,tau", [(0.1, 0.50605), (0.3, 0.51816)])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_taylor_green_64_vs_oracle(L, orc, ma, tau, storage, tol):
+    """The Taylor-Green problem at 64^3 with the 256^3 runs' Mach number and
+    tau (so Re = 400): 60 steps against the oracle, normwise moment error
+    (1e-12 FP64, 1e-5 FP32). At Ma 0.3 the collision works far from the
+    rest state (|u| up to 0.21)."""
+    n, steps = 64, 60
+    _, _, th = L.lattice()
+    F = wl.taylor_green(n, ma * np.sqrt(5.0 / 3.0 * th))
+    ctx = L.init([(n, n, n, tau)], *F.absolute(th), storage=storage)
+    ctx.step(steps)
+    m = ctx.moments()
+    assert ctx.status() == 0
+    ctx.free()
+    m_ref = cached_oracle_moments(orc, ("tgv64", ma), (n, n, n), tau, F, steps)
+    err = moment_error(m, m_ref)
+    say("TGV 64^3 Ma %.1f %s: normwise moment error %.2e" % (ma, storage, err))
+    assert err <= tol
+
+
+@pytest.mark.parametrize("storage,sr,tol", [("f64", False, 1e-12), ("f32", False, 1e-5), ("f16s", True, 1e-5)])
+def test_pulse_96_vs_oracle(L, orc, storage, sr, tol):
+    """The acoustic pulse recipe (eps 1e-3, b = 8, tau 0.6) on 96^3, 80 steps,
+    against the oracle: normwise moment error (1e-12 FP64, 1e-5 FP32 and
+    FP16-shifted with stochastic rounding, whose stored deviations carry
+    ~11 bits of an amplitude of 1e-3)."""
+    n, tau, steps = 96, 0.6, 80
+    _, _, th = L.lattice()
+    F = wl.gaussian_pulse(n, eps=1e-3, b=8.0)
+    ctx = L.init([(n, n, n, tau)], *F.absolute(th), storage=storage, stochastic=sr)
+    ctx.step(steps)
+    m = ctx.moments()
+    assert ctx.status() == 0
+    ctx.free()
+    m_ref = cached_oracle_moments(orc, "pulse96", (n, n, n), tau, F, steps)
+    err = moment_error(m, m_ref)
+    pert = float(np.max(np.abs(m_ref - m_ref.mean(axis=1, keepdims=True))))
+    say("pulse 96^3 %s%s: normwise moment error %.2e (%.2e of the perturbation)"
+        % (storage, "+SR" if sr else "", err, err * np.max(np.abs(m_ref)) / pert))
+    assert err <= tol
