@@ -33,8 +33,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=512, help="cells per edge of the periodic box")
-    ap.add_argument("--forms", default="f16s+sr,f32,f16s,f32+sr,f32s,bf16s+sr",
-                    help="storage forms (a '+sr' suffix: stochastic rounding); the first is the headline")
+    ap.add_argument("--forms", default="f16s+sr,f32,f16s,f32+sr,f32s,bf16s+sr,f16s+sr+e1,f32+e1",
+                    help="storage forms ('+sr': stochastic rounding, '+e1': series equilibrium E1 instead of "
+                         "the entropic E2); the first is the headline")
     ap.add_argument("--tau", type=float, default=0.6)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -92,11 +93,21 @@ def copy_reference(torch, gib, reps=5):
                       "gbs_read_plus_write": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
 
 
+def parse_form(form):
+    """'storage[+sr][+e1]': storage form, stochastic rounding, series
+    equilibrium E1 instead of the entropic E2."""
+    storage, *flags = form.split("+")
+    unknown = set(flags) - {"sr", "e1"}
+    if unknown:
+        raise SystemExit("unknown form flag(s) %s in %r" % (sorted(unknown), form))
+    return storage, "sr" in flags, "e1" in flags
+
+
 def time_form(lbm, torch, F, th, n, tau, form, steps, warmup, autotune):
-    storage, _, sr = form.partition("+")
+    storage, sr, e1 = parse_form(form)
     stream = torch.cuda.Stream()
     t0 = time.time()
-    ctx = lbm.init([(n, n, n, tau)], *F.absolute(th), storage=storage, stream=stream, stochastic=(sr == "sr"))
+    ctx = lbm.init([(n, n, n, tau)], *F.absolute(th), storage=storage, stream=stream, stochastic=sr, series=e1)
     init_s = time.time() - t0
     tune = None
     if autotune:
@@ -144,13 +155,13 @@ def time_batch(lbm, torch, form, steps, warmup, autotune):
     over every (box, tile), eager and replayed from captured graphs."""
     from paper_1909_08406_amd import workloads as wl
 
-    storage, _, sr = form.partition("+")
+    storage, sr, e1 = parse_form(form)
     specs = wl.batch_specs()
     cat = wl.concat([wl.batch_fields(b) for b in specs])
     _, _, th = lbm.lattice()
     stream = torch.cuda.Stream()
     ctx = lbm.init([(b.nx, b.ny, b.nz, b.tau) for b in specs], cat[0], cat[1], cat[2], cat[3], cat[4] * th,
-                   storage=storage, stream=stream, stochastic=(sr == "sr"))
+                   storage=storage, stream=stream, stochastic=sr, series=e1)
     del cat
     if autotune:
         ctx.autotune(reps=3)
@@ -261,7 +272,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": DTYPE[head["form"].partition("+")[0]] + (", stochastic rounding" if "+sr" in head["form"] else ""),
+        "dtype": DTYPE[parse_form(head["form"])[0]] + (", stochastic rounding" if parse_form(head["form"])[1] else ""),
         "data": "synthetic",
         "config": {"workload": "periodic acoustic pulse %d^3 cells (%d nodes), eps 1e-3, b 8, tau 0.6, %s"
                                % (n, head["nodes"], head["form"]),

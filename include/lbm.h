@@ -81,6 +81,14 @@ typedef enum {
                                            checked but not used. Steps run the default
                                            launch shape (256 threads, no hints);
                                            lbm_tuning.variant is not used. */
+#define LBM_FLAG_SERIES_EQUILIBRIUM 4u  /* the series equilibrium E1 (Sec. V): the zero-
+                                           velocity series to third order in theta/theta0 - 1
+                                           times the cubic velocity polynomial with A1, A2
+                                           from the lattice's fourth-moment errors M2, M2';
+                                           polynomial, no Newton solve. Mass and energy are
+                                           conserved, momentum up to O(u eta^k) terms.
+                                           Not with LBM_FLAG_ISOTHERMAL. Default launch
+                                           shape, as for the isothermal model. */
 
 /* Meaning of lbm_box.tau. */
 typedef enum {
@@ -302,7 +310,8 @@ int lbm_selftest(void);
  * Sec. V), run on the host with the same arithmetic in FP64 (precision 0)
  * or FP32 (precision 1) and `newton` Newton steps: f_out = C[f_in] for one
  * node's 41 populations (direct storage; inputs rounded to the precision).
- * flags: 0, or LBM_FLAG_ISOTHERMAL for the isothermal equilibrium.
+ * flags: 0, LBM_FLAG_ISOTHERMAL or LBM_FLAG_SERIES_EQUILIBRIUM for the
+ * isothermal or the series equilibrium.
  * For testing the arithmetic without a device. Errors: LBM_E_ARG.
  */
 int lbm_collide_host(int32_t precision, int32_t newton, uint32_t flags, double omega, const double *f_in,

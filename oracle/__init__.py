@@ -150,8 +150,8 @@ def equilibrium_iso(rho, u):
     return feq, lam, float(res[0]), it.value, rc
 
 
-# equilibrium models: 0 energy conserving (E2), 1 isothermal
-MODELS = {"thermal": 0, "isothermal": 1}
+# equilibrium models: 0 energy conserving (E2), 1 isothermal, 2 series (E1)
+MODELS = {"thermal": 0, "isothermal": 1, "series": 2}
 
 
 def _model(model):

@@ -419,8 +419,9 @@ void orc_equilibrium_series(double rho, double ux, double uy, double uz, double 
 /* ------------------------------------------------------------------------ */
 
 /* f* = f + omega (f_eq - f) for one node (Sec. II), with the equilibrium of
- * the node's rho, u, theta (model 0, energy conserving) or of its rho, u
- * (model 1, isothermal). */
+ * the node's rho, u, theta (model 0, energy conserving, E2), of its rho, u
+ * (model 1, isothermal) or the series equilibrium E1 of its rho, u, theta
+ * (model 2). */
 int orc_collide_node_model(const double *f, double omega, int model, double *out)
 {
     double m[5], feq[NQ];
@@ -430,6 +431,10 @@ int orc_collide_node_model(const double *f, double omega, int model, double *out
     int rc;
     if (model == 1) {
         rc = orc_equilibrium_iso(rho, ux, uy, uz, feq, NULL, NULL, NULL);
+    } else if (model == 2) {
+        double theta = (2.0 * m[4] / rho - (ux * ux + uy * uy + uz * uz)) / 3.0;
+        orc_equilibrium_series(rho, ux, uy, uz, theta, feq);
+        rc = 0;
     } else {
         /* E = (rho u^2 + 3 rho theta)/2 (Sec. II) */
         double theta = (2.0 * m[4] / rho - (ux * ux + uy * uy + uz * uz)) / 3.0;
@@ -521,7 +526,7 @@ void orc_push_map(int nx, int ny, int nz, int64_t *dst)
 }
 
 /* Populations at equilibrium with the given fields (all [node], FP64);
- * model 1 (isothermal) ignores theta. */
+ * model 0 E2, 1 isothermal (ignores theta), 2 series E1. */
 int orc_init_model(int nx, int ny, int nz, const double *rho, const double *ux, const double *uy,
                    const double *uz, const double *theta, int model, double *f)
 {
@@ -531,8 +536,10 @@ int orc_init_model(int nx, int ny, int nz, const double *rho, const double *ux, 
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int64_t n = 0; n < N; ++n) {
         double feq[NQ];
-        int rc = model == 1 ? orc_equilibrium_iso(rho[n], ux[n], uy[n], uz[n], feq, NULL, NULL, NULL)
-                            : orc_equilibrium(rho[n], ux[n], uy[n], uz[n], theta[n], feq, NULL, NULL, NULL);
+        int rc = 0;
+        if (model == 1) rc = orc_equilibrium_iso(rho[n], ux[n], uy[n], uz[n], feq, NULL, NULL, NULL);
+        else if (model == 2) orc_equilibrium_series(rho[n], ux[n], uy[n], uz[n], theta[n], feq);
+        else rc = orc_equilibrium(rho[n], ux[n], uy[n], uz[n], theta[n], feq, NULL, NULL, NULL);
         if (rc != 0) bad = 1;
         for (int q = 0; q < NQ; ++q) f[q * N + n] = feq[q];
     }

@@ -436,6 +436,94 @@ __host__ __device__ inline void newton_step(Mult<R>& m, const NodeDev<R>& st)
     m.g -= x3;
 }
 
+// ---------------------------------------------------------------------------
+// Series equilibrium E1 (Sec. V): f_eq,i = w_i rho f~_i(eta) P_i(u), with
+// the zero-velocity series to third order in eta = theta/theta0 - 1,
+//   f~ = 1 + eta/2 (x - 3) + eta^2/8 (x^2 - 10 x + 15)
+//          + eta^3/48 (x^3 - 21 x^2 + 105 x - 105),   x = c^2/theta0,
+// and the cubic velocity polynomial with uc = u.c/theta,
+//   P = 1 + uc + uc^2/2 + uc^3/6 - u^2/(2 theta) (1 - A1)
+//       - u^2 c^2 A1/(6 theta^2) + u^2 uc A2/(6 theta) - u^2 c^2 uc A1/(6 theta^2),
+//   A1 = (5/2) M2 / (1 + (5/2) M2),  A2 = 5 A1 (1 - M2) - (3 + M2' - 5 M2),
+// where M2, M2' are the relative errors of the fourth moments of f~ (sums
+// over the lattice). In deviation form eps_i = f~ P - 1 = dmul(T_s, Q_i),
+// T_s = f~ - 1 per shell and Q_i = P_i - 1 = alpha_s + uc (1 + beta_s +
+// uc (1/2 + uc/6)).
+// ---------------------------------------------------------------------------
+template <typename R>
+struct SeriesCoef {
+    R a[3];        // u / theta
+    R T[6];        // f~ - 1 per shell
+    R alpha[6];    // u-independent part of P - 1 per shell
+    R beta1[6];    // 1 + coefficient of uc u^2 per shell
+};
+
+__host__ __device__ constexpr double series_k(int s, int order)
+{
+    const double x = SHELL_C2[s] / THETA0;
+    return order == 1 ? 0.5 * (x - 3.0)
+         : order == 2 ? (x * x - 10.0 * x + 15.0) / 8.0
+                      : (x * x * x - 21.0 * x * x + 105.0 * x - 105.0) / 48.0;
+}
+
+// eta = theta/theta0 - 1 is passed in (formed from moment deviations by
+// the caller, free of the cancellation of theta/theta0 - 1).
+template <typename R>
+__host__ __device__ inline void series_coef(R ux, R uy, R uz, R eta, SeriesCoef<R>& sc)
+{
+    const R theta = R(THETA0) * (R(1) + eta);
+    R s4 = R(0), sxy = R(0);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        sc.T[s] = eta * (R(series_k(s, 1)) + eta * (R(series_k(s, 2)) + eta * R(series_k(s, 3))));
+        s4 += R(SHELL_C4[s] / (15.0 * THETA0 * THETA0)) * sc.T[s];
+        sxy += R(SHELL_CXCY[s] / (THETA0 * THETA0)) * sc.T[s];
+    }
+    // M2 = sum w c^4 (1 + T)/(15 theta^2) - 1 and M2' likewise, formed from
+    // the reference-state values (exact lattice sums) and the deviations
+    constexpr double M20 = (SHELL_C4[0] + SHELL_C4[1] + SHELL_C4[2] + SHELL_C4[3] + SHELL_C4[4] + SHELL_C4[5]) /
+                           (15.0 * THETA0 * THETA0) - 1.0;
+    constexpr double MXY0 = (SHELL_CXCY[0] + SHELL_CXCY[1] + SHELL_CXCY[2] + SHELL_CXCY[3] + SHELL_CXCY[4] +
+                             SHELL_CXCY[5]) / (THETA0 * THETA0) - 1.0;
+    const R ie2 = R(1) / ((R(1) + eta) * (R(1) + eta));
+    const R de = eta * (R(2) + eta);
+    const R M2 = (R(M20) + s4 - de) * ie2;
+    const R M2p = (R(MXY0) + sxy - de) * ie2;
+    const R A1 = R(2.5) * M2 / (R(1) + R(2.5) * M2);
+    const R A2 = R(5) * A1 * (R(1) - M2) - (R(3) + M2p - R(5) * M2);
+    const R ith = R(1) / theta;
+    sc.a[0] = ux * ith;
+    sc.a[1] = uy * ith;
+    sc.a[2] = uz * ith;
+    const R U = (ux * ux + uy * uy + uz * uz) * ith;  // u^2 / theta
+    const R uA1 = U * A1 * ith * R(1.0 / 6.0);        // u^2 A1 / (6 theta^2)
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        sc.alpha[s] = -R(0.5) * U * (R(1) - A1) - uA1 * R(SHELL_C2[s]);
+        sc.beta1[s] = R(1) + U * A2 * R(1.0 / 6.0) - uA1 * R(SHELL_C2[s]);
+    }
+}
+
+// eps_q = f~ P - 1 for velocity q
+template <int q, typename R>
+__host__ __device__ inline R series_eps(const SeriesCoef<R>& sc)
+{
+    constexpr HalfVel v = VEL[q];
+    constexpr int s = v.shell;
+    if constexpr (s == 0) {
+        return dmul(sc.T[0], sc.alpha[0]);
+    } else {
+        R uc = R(0);
+        if constexpr (v.x != 0) uc = fma(sc.a[0], R(0.5 * v.x), uc);
+        if constexpr (v.y != 0) uc = fma(sc.a[1], R(0.5 * v.y), uc);
+        if constexpr (v.z != 0) uc = fma(sc.a[2], R(0.5 * v.z), uc);
+        R t = fma(uc, R(1.0 / 6.0), R(0.5));
+        t = fma(uc, t, sc.beta1[s]);
+        const R Qd = fma(uc, t, sc.alpha[s]);
+        return dmul(sc.T[s], Qd);
+    }
+}
+
 // e^{b.c_q - g c_q^2} - 1 for velocity q, from the shell structure.
 template <int q, typename R>
 __host__ __device__ inline R gibbs_dev(const Shells<R>& S)
@@ -636,7 +724,7 @@ struct StepParams {
     uint32_t seed;
     uint32_t node0;        // index of the box's first node in the context (random-bit stream)
     const uint32_t* step_base;  // null, or a device counter added to step (graph replays)
-    uint32_t isothermal;   // 1: equilibrium under mass and momentum only (temperature theta0)
+    uint32_t model;        // equilibrium: 0 energy conserving (E2), 1 isothermal, 2 series (E1)
 };
 
 // Counter-based random bits for stochastic rounding: one hash per node and

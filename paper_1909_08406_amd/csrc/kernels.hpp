@@ -49,9 +49,13 @@ struct CollideConst {
     R omw[6];        // omega w_s rho_ref 2^{k_s} (shifted) or omega w_s
 };
 
-// ISO: the isothermal equilibrium (mass and momentum only) instead of the
-// energy-conserving one.
-template <typename R, bool SHIFTED, int NEWTON, bool ISO = false>
+// Equilibrium models: the energy-conserving entropic equilibrium E2, the
+// isothermal one (mass and momentum only) and the series equilibrium E1.
+constexpr int MODEL_E2 = 0;
+constexpr int MODEL_ISO = 1;
+constexpr int MODEL_SERIES = 2;
+
+template <typename R, bool SHIFTED, int NEWTON, int MODEL = MODEL_E2>
 __host__ __device__ inline void collide(const R x[Q], R y[Q], const CollideConst<R>& cc, R& rho_out, R& theta_out)
 {
     ShellSums<R> SS;
@@ -92,8 +96,33 @@ __host__ __device__ inline void collide(const R x[Q], R y[Q], const CollideConst
     rho_out = st.rho;
     theta_out = theta;
 
+    const R om = cc.om, om1 = R(1) - om;
+    // f_eq,q - w_q rho_ref = w_q rho_ref D_q; relaxation of population q
+    auto relax = [&](auto qc, R D) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int sh = VEL[q].shell;
+        if constexpr (SHIFTED) y[q] = fma(om1, x[q], cc.omw[sh] * D);                // h* = (1-w) h + w 2^k d_eq
+        else y[q] = fma(cc.omw[sh], D, -om * (x[q] - R(weight(q))));                  // f* - f = w (f_eq - f)
+    };
+    if constexpr (MODEL == MODEL_SERIES) {
+        // 1 + D_q = (1 + eps_q) rho / (rho_ref sum_i w_i)
+        // eta = theta/theta0 - 1 from the deviations of 2E and rho:
+        // 3 theta0 rho eta = rho_ref (sum w c^2 - 3 theta0 sum w) + de2 - 3 theta0 drho - rho u^2
+        constexpr double E2_OFF = SUM_WC2 - 3.0 * THETA0 * SUM_W;
+        const R eta = (st.rho_ref * R(E2_OFF) + st.de2 - R(3.0 * THETA0) * st.drho -
+                       st.rho * (ux * ux + uy * uy + uz * uz)) *
+                      st.irho * R(1.0 / (3.0 * THETA0));
+        SeriesCoef<R> sc;
+        series_coef<R>(ux, uy, uz, eta, sc);
+        const R kap = st.drho / (st.rho_ref * R(SUM_W));
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            relax(qc, dmul(series_eps<q, R>(sc), kap));
+        });
+        return;
+    }
     Mult<R> m;
-    if constexpr (ISO) {
+    if constexpr (MODEL == MODEL_ISO) {
         // isothermal: g = 0, Maxwellian guess at theta0
         m.b[0] = ux * R(1.0 / THETA0);
         m.b[1] = uy * R(1.0 / THETA0);
@@ -111,17 +140,13 @@ __host__ __device__ inline void collide(const R x[Q], R y[Q], const CollideConst
         for (int it = 0; it < NEWTON; ++it) newton_step<R>(m, st);
     }
 
-    // f_eq,q - w_q rho_ref = w_q rho_ref D_q with 1 + D_q = (1 + eps_q)(1 + kappa)
+    // 1 + D_q = (1 + eps_q)(1 + kappa)
     Shells<R> S;
     shells_at<R>(m, S);
     const R kap = kappa_of<R>(st, S);
-    const R om = cc.om, om1 = R(1) - om;
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        constexpr int sh = VEL[q].shell;
-        const R D = dmul(gibbs_dev<q, R>(S), kap);
-        if constexpr (SHIFTED) y[q] = fma(om1, x[q], cc.omw[sh] * D);                // h* = (1-w) h + w 2^k d_eq
-        else y[q] = fma(cc.omw[sh], D, -om * (x[q] - R(weight(q))));                  // f* - f = w (f_eq - f)
+        relax(qc, dmul(gibbs_dev<q, R>(S), kap));
     });
 }
 
@@ -171,7 +196,7 @@ __device__ inline void st_hint(T* p, T v, int nt)
 // storage type in out (round to nearest, or stochastic rounding with bits
 // drawn for node `nid` of the context at the launch's step); raises the
 // flag for an unrealisable node.
-template <class ST, int NEWTON, bool SR, bool ISO>
+template <class ST, int NEWTON, bool SR, int MODEL>
 __device__ inline void collide_encode(const typename ST::R x[Q], typename ST::T out[Q], const StepParams& p,
                                       uint32_t nid)
 {
@@ -185,7 +210,7 @@ __device__ inline void collide_encode(const typename ST::R x[Q], typename ST::T 
         cc.omw[s] = ST::shifted ? R(p.omw[s]) : cc.om * R(SHELL_W[s]);
     }
     R y[Q], rho, theta;
-    collide<R, ST::shifted, NEWTON, ISO>(x, y, cc, rho, theta);
+    collide<R, ST::shifted, NEWTON, MODEL>(x, y, cc, rho, theta);
     flag_bad<R>(p, rho, theta);
     uint32_t rs = 0, rw = 0;
     if constexpr (SR) {
@@ -210,7 +235,7 @@ __device__ inline void collide_encode(const typename ST::R x[Q], typename ST::T 
 
 // The step of node n of one box: src and dst are the box's first q-block
 // in the current and the other population buffer.
-template <class ST, int NEWTON, int FL, bool SR, bool ISO>
+template <class ST, int NEWTON, int FL, bool SR, int MODEL>
 __device__ inline void step_node(const char* __restrict__ src, char* __restrict__ dst, const StepParams& p,
                                  uint32_t n)
 {
@@ -228,7 +253,7 @@ __device__ inline void step_node(const char* __restrict__ src, char* __restrict_
                                   FL & FL_NT_LOAD));
     });
     T out[Q];
-    collide_encode<ST, NEWTON, SR, ISO>(x, out, p, p.node0 + n);
+    collide_encode<ST, NEWTON, SR, MODEL>(x, out, p, p.node0 + n);
     const uint32_t nbytes = n * uint32_t(sizeof(T));
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
@@ -237,14 +262,14 @@ __device__ inline void step_node(const char* __restrict__ src, char* __restrict_
 }
 
 // One box per launch; fin/fout point at the box's first q-block.
-template <class ST, int NEWTON, int BLK, int FL, bool SR, bool ISO = false>
+template <class ST, int NEWTON, int BLK, int FL, bool SR, int MODEL = MODEL_E2>
 __global__ __launch_bounds__(BLK) void k_step(const typename ST::T* __restrict__ fin,
                                               typename ST::T* __restrict__ fout, StepParams p)
 {
     const uint32_t blk = p.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     const uint32_t n = blk * BLK + threadIdx.x;
     if (n >= p.g.N) return;
-    step_node<ST, NEWTON, FL, SR, ISO>(reinterpret_cast<const char*>(fin), reinterpret_cast<char*>(fout), p, n);
+    step_node<ST, NEWTON, FL, SR, MODEL>(reinterpret_cast<const char*>(fin), reinterpret_cast<char*>(fout), p, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -259,7 +284,7 @@ struct BatchBox {
     uint64_t offset;  // element offset of the box in a population buffer
 };
 
-template <class ST, int NEWTON, int BLK, int FL, bool SR, bool ISO = false>
+template <class ST, int NEWTON, int BLK, int FL, bool SR, int MODEL = MODEL_E2>
 __global__ __launch_bounds__(BLK) void k_step_batch(const typename ST::T* __restrict__ fin,
                                                     typename ST::T* __restrict__ fout,
                                                     const BatchBox* __restrict__ boxes,
@@ -274,7 +299,7 @@ __global__ __launch_bounds__(BLK) void k_step_batch(const typename ST::T* __rest
     StepParams p = B.p;
     p.step = step;
     p.step_base = step_base;
-    step_node<ST, NEWTON, FL, SR, ISO>(reinterpret_cast<const char*>(fin + B.offset),
+    step_node<ST, NEWTON, FL, SR, MODEL>(reinterpret_cast<const char*>(fin + B.offset),
                                        reinterpret_cast<char*>(fout + B.offset), p, n);
 }
 
@@ -293,9 +318,9 @@ constexpr int INIT_NEWTON = 6;
 
 // Deviations D_q (f_eq,q = w_q rho_ref (1 + D_q)) of the equilibrium of
 // (rho, u, theta) in FP64, relative to the reference state w_q rho_ref.
-// iso: the isothermal equilibrium of (rho, u) (theta unused).
+// model: MODEL_E2, MODEL_ISO (theta unused) or MODEL_SERIES.
 __device__ inline void equilibrium_dev_f64(double rho, double ux, double uy, double uz, double theta,
-                                           double rho_ref, bool iso, double D[Q])
+                                           double rho_ref, int model, double D[Q])
 {
     NodeDev<double> st;
     st.rho_ref = rho_ref;
@@ -306,8 +331,18 @@ __device__ inline void equilibrium_dev_f64(double rho, double ux, double uy, dou
     st.j[1] = rho * uy;
     st.j[2] = rho * uz;
     st.de2 = rho * (ux * ux + uy * uy + uz * uz + 3.0 * theta) - rho_ref * SUM_WC2;
+    if (model == MODEL_SERIES) {
+        SeriesCoef<double> sc;
+        series_coef<double>(ux, uy, uz, theta / THETA0 - 1.0, sc);
+        const double kap = st.drho / (rho_ref * SUM_W);
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            D[q] = dmul(series_eps<q, double>(sc), kap);
+        });
+        return;
+    }
     Mult<double> m;
-    if (iso) {
+    if (model == MODEL_ISO) {
         m.b[0] = ux / THETA0;
         m.b[1] = uy / THETA0;
         m.b[2] = uz / THETA0;
@@ -370,7 +405,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(typename ST::T* __restrict__ f, 
         // storage reference: rho0 for the shifted forms, the weights themselves otherwise
         const double rref = ST::shifted ? p.rho_ref : 1.0;
         double D[Q];
-        equilibrium_dev_f64(rho, ux, uy, uz, th, rref, p.isothermal != 0, D);
+        equilibrium_dev_f64(rho, ux, uy, uz, th, rref, int(p.model), D);
         bool bad = false;
         static_for<Q>([&](auto qc) {
             constexpr int q = decltype(qc)::value;

@@ -75,6 +75,30 @@ constexpr double sum_wc2_value()
 constexpr double SUM_W = sum_w_value();
 constexpr double SUM_WC2 = sum_wc2_value();
 
+// Per-shell sums of the series equilibrium (Sec. V): sum_{i in shell}
+// w_i c_i^4 and sum_{i in shell} w_i c_ix^2 c_iy^2.
+constexpr double shell_sum_c4(int s)
+{
+    double a = 0.0;
+    for (int q = 0; q < Q; ++q) {
+        if (VEL[q].shell != s) continue;
+        const double c2 = 0.25 * (VEL[q].x * VEL[q].x + VEL[q].y * VEL[q].y + VEL[q].z * VEL[q].z);
+        a += weight(q) * c2 * c2;
+    }
+    return a;
+}
+constexpr double shell_sum_cxcy(int s)
+{
+    double a = 0.0;
+    for (int q = 0; q < Q; ++q)
+        if (VEL[q].shell == s) a += weight(q) * 0.0625 * (VEL[q].x * VEL[q].x) * (VEL[q].y * VEL[q].y);
+    return a;
+}
+constexpr double SHELL_C4[6] = {shell_sum_c4(0), shell_sum_c4(1), shell_sum_c4(2),
+                                shell_sum_c4(3), shell_sum_c4(4), shell_sum_c4(5)};
+constexpr double SHELL_CXCY[6] = {shell_sum_cxcy(0), shell_sum_cxcy(1), shell_sum_cxcy(2),
+                                  shell_sum_cxcy(3), shell_sum_cxcy(4), shell_sum_cxcy(5)};
+
 // Power-of-two exponent per shell used by the shifted storage so that
 // (f - w rho0) 2^k has magnitude ~ (relative deviation) 2^k_amp:
 // k_shell = round(-log2 w_shell).

@@ -75,7 +75,9 @@ int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
     if (eb == 0) return LBM_E_ARG;
     if (opts->tau_conv != LBM_TAU_LB && opts->tau_conv != LBM_TAU_PAPER) return LBM_E_ARG;
     if (opts->newton_iters < 0 || opts->newton_iters > 4) return LBM_E_ARG;
-    if (opts->flags & ~uint32_t(LBM_FLAG_STOCHASTIC_ROUNDING | LBM_FLAG_ISOTHERMAL)) return LBM_E_ARG;
+    if (opts->flags & ~uint32_t(LBM_FLAG_STOCHASTIC_ROUNDING | LBM_FLAG_ISOTHERMAL | LBM_FLAG_SERIES_EQUILIBRIUM))
+        return LBM_E_ARG;
+    if ((opts->flags & LBM_FLAG_ISOTHERMAL) && (opts->flags & LBM_FLAG_SERIES_EQUILIBRIUM)) return LBM_E_ARG;
     if ((opts->flags & LBM_FLAG_STOCHASTIC_ROUNDING) &&
         !(opts->storage == LBM_F32 || opts->storage == LBM_F16_SHIFT || opts->storage == LBM_BF16_SHIFT))
         return LBM_E_ARG;
@@ -257,14 +259,14 @@ int enqueue_step(lbm_ctx* ctx, int from, uint32_t step, const uint32_t* step_bas
                                 std::is_same<ST, StoreBF16S>::value;
         return with_newton(ctx->newton, [&](auto nw) {
             constexpr int NEWTON = decltype(nw)::value;
-            auto launch = [&](auto sr, auto iso, auto blk, auto fl) {
+            auto launch = [&](auto sr, auto model, auto blk, auto fl) {
                 constexpr bool SR = decltype(sr)::value;
-                constexpr bool ISO = decltype(iso)::value;
+                constexpr int MODEL = decltype(model)::value;
                 constexpr int BLK = decltype(blk)::value;
                 constexpr int FL = decltype(fl)::value;
                 if (ctx->schedule == LBM_SCHEDULE_BATCHED) {
                     const int i = blk_index(BLK);
-                    hipLaunchKernelGGL((k_step_batch<ST, NEWTON, BLK, FL, SR, ISO>), dim3(uint32_t(ctx->L.ntiles[i])),
+                    hipLaunchKernelGGL((k_step_batch<ST, NEWTON, BLK, FL, SR, MODEL>), dim3(uint32_t(ctx->L.ntiles[i])),
                                        dim3(BLK), 0, s, in, out, ctx->table, ctx->tiles[i], ctx->base.xcd_remap, step,
                                        step_base);
                 } else {
@@ -272,19 +274,25 @@ int enqueue_step(lbm_ctx* ctx, int from, uint32_t step, const uint32_t* step_bas
                         StepParams p = ctx->params(b);
                         p.step = step;
                         p.step_base = step_base;
-                        hipLaunchKernelGGL((k_step<ST, NEWTON, BLK, FL, SR, ISO>),
+                        hipLaunchKernelGGL((k_step<ST, NEWTON, BLK, FL, SR, MODEL>),
                                            dim3(uint32_t((b.nodes + BLK - 1) / BLK)), dim3(BLK), 0, s,
                                            in + b.offset, out + b.offset, p);
                     }
                 }
             };
             auto go = [&](auto sr) -> int {
-                if (ctx->base.isothermal) {
-                    // the isothermal model runs the default launch shape
-                    launch(sr, std::true_type{}, std::integral_constant<int, 256>{}, std::integral_constant<int, 0>{});
+                using std::integral_constant;
+                if (ctx->base.model != MODEL_E2) {
+                    // the isothermal and series models run the default launch shape
+                    const integral_constant<int, 256> blk;
+                    const integral_constant<int, 0> fl;
+                    if (ctx->base.model == MODEL_ISO) launch(sr, integral_constant<int, MODEL_ISO>{}, blk, fl);
+                    else launch(sr, integral_constant<int, MODEL_SERIES>{}, blk, fl);
                     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
                 }
-                return with_variant(ctx->variant, [&](auto blk, auto fl) { launch(sr, std::false_type{}, blk, fl); });
+                return with_variant(ctx->variant, [&](auto blk, auto fl) {
+                    launch(sr, integral_constant<int, MODEL_E2>{}, blk, fl);
+                });
             };
             if constexpr (has_sr) {
                 if (ctx->stochastic) return go(std::true_type{});
@@ -412,7 +420,7 @@ void set_shift(lbm_ctx* ctx)
 
 namespace {
 template <typename R, int NEWTON>
-void collide_host(double omega, bool iso, const double* in, double* out)
+void collide_host(double omega, int model, const double* in, double* out)
 {
     CollideConst<R> cc;
     cc.om = R(omega);
@@ -423,8 +431,9 @@ void collide_host(double omega, bool iso, const double* in, double* out)
     }
     R x[Q], y[Q], rho, theta;
     for (int q = 0; q < Q; ++q) x[q] = R(in[q]);
-    if (iso) collide<R, false, NEWTON, true>(x, y, cc, rho, theta);
-    else collide<R, false, NEWTON, false>(x, y, cc, rho, theta);
+    if (model == MODEL_ISO) collide<R, false, NEWTON, MODEL_ISO>(x, y, cc, rho, theta);
+    else if (model == MODEL_SERIES) collide<R, false, NEWTON, MODEL_SERIES>(x, y, cc, rho, theta);
+    else collide<R, false, NEWTON, MODEL_E2>(x, y, cc, rho, theta);
     for (int q = 0; q < Q; ++q) out[q] = double(R(x[q] + y[q]));
 }
 }  // namespace
@@ -533,7 +542,8 @@ static int init_impl(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const 
 
     ctx->base.flag = ctx->flag;
     ctx->base.xcd_remap = 1;
-    ctx->base.isothermal = (opts->flags & LBM_FLAG_ISOTHERMAL) ? 1u : 0u;
+    ctx->base.model = (opts->flags & LBM_FLAG_ISOTHERMAL) ? uint32_t(MODEL_ISO)
+                      : (opts->flags & LBM_FLAG_SERIES_EQUILIBRIUM) ? uint32_t(MODEL_SERIES) : uint32_t(MODEL_E2);
     ctx->base.seed = opts->seed;
     ctx->base.rho_ref = shifted ? ctx->rho0 : 0.0;
     ctx->rho_ref_storage = ctx->base.rho_ref;
@@ -841,12 +851,14 @@ int lbm_get_info(lbm_ctx* ctx, lbm_info* info)
     info->storage = ctx->storage;
     info->newton_iters = ctx->newton;
     info->shift_exp = (ctx->storage == LBM_F16_SHIFT || ctx->storage == LBM_BF16_SHIFT) ? ctx->kamp : 0;
-    info->flags = (ctx->stochastic ? LBM_FLAG_STOCHASTIC_ROUNDING : 0u) | (ctx->base.isothermal ? LBM_FLAG_ISOTHERMAL : 0u);
+    info->flags = (ctx->stochastic ? LBM_FLAG_STOCHASTIC_ROUNDING : 0u) |
+                  (ctx->base.model == MODEL_ISO ? LBM_FLAG_ISOTHERMAL : 0u) |
+                  (ctx->base.model == MODEL_SERIES ? LBM_FLAG_SERIES_EQUILIBRIUM : 0u);
     info->steps_done = ctx->steps_done;
     info->nboxes = int32_t(ctx->boxes.size());
     info->nodes = int64_t(ctx->L.elems / Q);
     info->bytes_per_step = int64_t(2 * ctx->L.elems * uint64_t(elem_bytes(ctx->storage)));
-    info->block_threads = ctx->base.isothermal ? 256 : VARIANTS[ctx->variant].blk;
+    info->block_threads = ctx->base.model != MODEL_E2 ? 256 : VARIANTS[ctx->variant].blk;
     info->variant = ctx->variant;
     info->device_bytes = ctx->L.total;
     return LBM_OK;
@@ -973,9 +985,11 @@ int lbm_collide_host(int32_t precision, int32_t newton, uint32_t flags, double o
                      double* f_out)
 {
     if (!f_in || !f_out || (precision != 0 && precision != 1) || newton < 0 || newton > 4 ||
-        (flags & ~uint32_t(LBM_FLAG_ISOTHERMAL)))
+        (flags & ~uint32_t(LBM_FLAG_ISOTHERMAL | LBM_FLAG_SERIES_EQUILIBRIUM)) ||
+        ((flags & LBM_FLAG_ISOTHERMAL) && (flags & LBM_FLAG_SERIES_EQUILIBRIUM)))
         return LBM_E_ARG;
-    const bool iso = (flags & LBM_FLAG_ISOTHERMAL) != 0;
+    const int iso = (flags & LBM_FLAG_ISOTHERMAL) ? MODEL_ISO : (flags & LBM_FLAG_SERIES_EQUILIBRIUM) ? MODEL_SERIES
+                                                                                                      : MODEL_E2;
     if (precision == 0) {
         switch (newton) {
             case 0: collide_host<double, 0>(omega, iso, f_in, f_out); break;

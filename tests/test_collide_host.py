@@ -65,3 +65,23 @@ def test_host_isothermal_collision_matches_oracle(orc, precision, newton, tol, c
     # the rest state rho w is a fixed point
     g = L.collide_host(1.2 * w, 1 / 0.6, precision, newton, isothermal=True)
     assert np.max(np.abs(g - 1.2 * w)) < tol
+
+
+@pytest.mark.parametrize("precision,newton,tol,cons_tol", [("f64", 0, 2e-15, 2e-15), ("f32", 0, 4e-8, 6e-8)])
+def test_host_series_collision_matches_oracle(orc, precision, newton, tol, cons_tol):
+    """Series equilibrium E1 (Sec. V): the kernel's collision against the
+    oracle's for |u| <= 0.1 (the series' range); mass and energy kept to the
+    rounding of the arithmetic, and the momentum change equal to the
+    oracle's (E1 is not exactly momentum-conserving when theta differs from
+    theta0)."""
+    c, w, th = orc.lattice()
+    for amp, f in _cases(orc, seed=4):
+        if amp > 0.1:
+            continue  # beyond the series' range: its own truncation error is ~u^4
+        fin = f.astype(np.float32).astype(np.float64) if precision == "f32" else f
+        g = L.collide_host(f, 1 / 0.6, precision, newton, series=True)
+        ref = orc.collide_node(fin, 1 / 0.6, model="series")
+        assert np.max(np.abs(g - ref)) < tol, amp
+        m_in, m_g, m_ref = _moments(fin, c), _moments(g, c), _moments(ref, c)
+        assert abs(m_g[0] - m_in[0]) < cons_tol and abs(m_g[4] - m_in[4]) < cons_tol, amp
+        assert np.max(np.abs(m_g[1:4] - m_ref[1:4])) < cons_tol, amp
