@@ -3,6 +3,8 @@
 // debug pull map.
 #pragma once
 
+#include <type_traits>
+
 #include "device.hpp"
 
 namespace lbm {
@@ -55,11 +57,25 @@ constexpr int MODEL_E2 = 0;
 constexpr int MODEL_ISO = 1;
 constexpr int MODEL_SERIES = 2;
 
+// For direct storage in FP64 x is overwritten by the deviations
+// d_q = f_q - w_q (exact while f_q is within a factor two of w_q), so only d
+// stays live through the equilibrium solve (214 instead of 256 registers:
+// two wavefronts per SIMD) and the caller restores f_q = d_q + w_q. In FP32
+// both are kept (measured marginally faster).
+template <typename R>
+constexpr bool DEV_IN_PLACE = std::is_same<R, double>::value;
+
 template <typename R, bool SHIFTED, int NEWTON, int MODEL = MODEL_E2>
-__host__ __device__ inline void collide(const R x[Q], R y[Q], const CollideConst<R>& cc, R& rho_out, R& theta_out)
+__host__ __device__ inline void collide(R x[Q], R y[Q], const CollideConst<R>& cc, R& rho_out, R& theta_out)
 {
     ShellSums<R> SS;
     if constexpr (SHIFTED) {
+        shell_sums<R>(x, SS);
+    } else if constexpr (DEV_IN_PLACE<R>) {
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            x[q] = x[q] - R(weight(q));
+        });
         shell_sums<R>(x, SS);
     } else {
         R d[Q];
@@ -102,7 +118,8 @@ __host__ __device__ inline void collide(const R x[Q], R y[Q], const CollideConst
         constexpr int q = decltype(qc)::value;
         constexpr int sh = VEL[q].shell;
         if constexpr (SHIFTED) y[q] = fma(om1, x[q], cc.omw[sh] * D);                // h* = (1-w) h + w 2^k d_eq
-        else y[q] = fma(cc.omw[sh], D, -om * (x[q] - R(weight(q))));                  // f* - f = w (f_eq - f)
+        else if constexpr (DEV_IN_PLACE<R>) y[q] = fma(cc.omw[sh], D, -om * x[q]);  // f* - f = w (f_eq - f)
+        else y[q] = fma(cc.omw[sh], D, -om * (x[q] - R(weight(q))));
     };
     if constexpr (MODEL == MODEL_SERIES) {
         // 1 + D_q = (1 + eps_q) rho / (rho_ref sum_i w_i)
@@ -196,8 +213,9 @@ __device__ inline void st_hint(T* p, T v, int nt)
 // storage type in out (round to nearest, or stochastic rounding with bits
 // drawn for node `nid` of the context at the launch's step); raises the
 // flag for an unrealisable node.
+// x: decoded stored values (overwritten by the collision for direct storage).
 template <class ST, int NEWTON, bool SR, int MODEL>
-__device__ inline void collide_encode(const typename ST::R x[Q], typename ST::T out[Q], const StepParams& p,
+__device__ inline void collide_encode(typename ST::R x[Q], typename ST::T out[Q], const StepParams& p,
                                       uint32_t nid)
 {
     using R = typename ST::R;
@@ -225,9 +243,10 @@ __device__ inline void collide_encode(const typename ST::R x[Q], typename ST::T 
             if constexpr (q % 2 == 0) rw = xorshift32(rs);
             const uint32_t rb = (q % 2 == 0) ? (rw & 0xffffu) : (rw >> 16);
             if constexpr (ST::shifted) out[q] = ST::encode_sr(y[q], rb);
-            else out[q] = sr_add(x[q], y[q], rb);
+            else out[q] = sr_add(x[q], y[q], rb);  // stochastic rounding exists for FP32 only
         } else {
             if constexpr (ST::shifted) out[q] = ST::encode(y[q]);
+            else if constexpr (DEV_IN_PLACE<R>) out[q] = ST::encode((x[q] + R(weight(q))) + y[q]);  // f = d + w
             else out[q] = ST::encode(x[q] + y[q]);
         }
     });

@@ -434,7 +434,9 @@ void collide_host(double omega, int model, const double* in, double* out)
     if (model == MODEL_ISO) collide<R, false, NEWTON, MODEL_ISO>(x, y, cc, rho, theta);
     else if (model == MODEL_SERIES) collide<R, false, NEWTON, MODEL_SERIES>(x, y, cc, rho, theta);
     else collide<R, false, NEWTON, MODEL_E2>(x, y, cc, rho, theta);
-    for (int q = 0; q < Q; ++q) out[q] = double(R(x[q] + y[q]));
+    for (int q = 0; q < Q; ++q)
+        out[q] = DEV_IN_PLACE<R> ? double(R((x[q] + R(SHELL_W[VEL[q].shell])) + y[q]))  // x holds f - w
+                                 : double(R(x[q] + y[q]));
 }
 }  // namespace
 
