@@ -65,8 +65,14 @@ constexpr int MODEL_SERIES = 2;
 template <typename R>
 constexpr bool DEV_IN_PLACE = std::is_same<R, double>::value;
 
-template <typename R, bool SHIFTED, int NEWTON, int MODEL = MODEL_E2>
-__host__ __device__ inline void collide(R x[Q], R y[Q], const CollideConst<R>& cc, R& rho_out, R& theta_out)
+// The relaxation reads the stored values again through xr(q) when one is
+// given (a second decode of values the caller keeps in a compact form), so
+// the decoded x need not stay live through the equilibrium solve.
+struct NoReload {};
+
+template <typename R, bool SHIFTED, int NEWTON, int MODEL = MODEL_E2, class XR = NoReload>
+__host__ __device__ inline void collide(R x[Q], R y[Q], const CollideConst<R>& cc, R& rho_out, R& theta_out,
+                                        const XR& xr = XR())
 {
     ShellSums<R> SS;
     if constexpr (SHIFTED) {
@@ -117,7 +123,8 @@ __host__ __device__ inline void collide(R x[Q], R y[Q], const CollideConst<R>& c
     auto relax = [&](auto qc, R D) {
         constexpr int q = decltype(qc)::value;
         constexpr int sh = VEL[q].shell;
-        if constexpr (SHIFTED) y[q] = fma(om1, x[q], cc.omw[sh] * D);                // h* = (1-w) h + w 2^k d_eq
+        if constexpr (SHIFTED && !std::is_same<XR, NoReload>::value) y[q] = fma(om1, xr(qc), cc.omw[sh] * D);
+        else if constexpr (SHIFTED) y[q] = fma(om1, x[q], cc.omw[sh] * D);          // h* = (1-w) h + w 2^k d_eq
         else if constexpr (DEV_IN_PLACE<R>) y[q] = fma(cc.omw[sh], D, -om * x[q]);  // f* - f = w (f_eq - f)
         else y[q] = fma(cc.omw[sh], D, -om * (x[q] - R(weight(q))));
     };
@@ -214,9 +221,9 @@ __device__ inline void st_hint(T* p, T v, int nt)
 // drawn for node `nid` of the context at the launch's step); raises the
 // flag for an unrealisable node.
 // x: decoded stored values (overwritten by the collision for direct storage).
-template <class ST, int NEWTON, bool SR, int MODEL>
+template <class ST, int NEWTON, bool SR, int MODEL, class XR = NoReload>
 __device__ inline void collide_encode(typename ST::R x[Q], typename ST::T out[Q], const StepParams& p,
-                                      uint32_t nid)
+                                      uint32_t nid, const XR& xr = XR())
 {
     using R = typename ST::R;
     CollideConst<R> cc;
@@ -228,7 +235,7 @@ __device__ inline void collide_encode(typename ST::R x[Q], typename ST::T out[Q]
         cc.omw[s] = ST::shifted ? R(p.omw[s]) : cc.om * R(SHELL_W[s]);
     }
     R y[Q], rho, theta;
-    collide<R, ST::shifted, NEWTON, MODEL>(x, y, cc, rho, theta);
+    collide<R, ST::shifted, NEWTON, MODEL>(x, y, cc, rho, theta, xr);
     flag_bad<R>(p, rho, theta);
     uint32_t rs = 0, rw = 0;
     if constexpr (SR) {
@@ -266,13 +273,40 @@ __device__ inline void step_node(const char* __restrict__ src, char* __restrict_
     const uint64_t qbytes = uint64_t(p.g.N) * sizeof(T);
 
     R x[Q];
-    static_for<Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        x[q] = ST::decode(ld_hint(reinterpret_cast<const T*>(src + q * qbytes + uint64_t(pull_src<q>(nb))),
-                                  FL & FL_NT_LOAD));
-    });
     T out[Q];
-    collide_encode<ST, NEWTON, SR, MODEL>(x, out, p, p.node0 + n);
+    if constexpr (sizeof(T) == 2 && !SR) {
+        // 16-bit storage, round to nearest: the raw values are also kept two
+        // per 32-bit register and decoded again for the relaxation (fewer
+        // live registers through the equilibrium solve). Measured faster for
+        // round to nearest and slower with stochastic rounding, whose
+        // encoding adds its own live values.
+        constexpr int QP = (Q + 1) / 2;
+        uint32_t pk[QP];
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const T raw = ld_hint(reinterpret_cast<const T*>(src + q * qbytes + uint64_t(pull_src<q>(nb))),
+                                  FL & FL_NT_LOAD);
+            x[q] = ST::decode(raw);
+            const uint32_t b = __builtin_bit_cast(uint16_t, raw);
+            if constexpr (q % 2 == 0) pk[q / 2] = b;
+            else pk[q / 2] |= b << 16;
+        });
+        // keep the packed words opaque, so the relaxation cannot reuse x
+#pragma unroll
+        for (int k = 0; k < QP; ++k) asm volatile("" : "+v"(pk[k]));
+        auto xr = [&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            return ST::decode(__builtin_bit_cast(T, uint16_t(pk[q / 2] >> (16 * (q % 2)))));
+        };
+        collide_encode<ST, NEWTON, SR, MODEL>(x, out, p, p.node0 + n, xr);
+    } else {
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            x[q] = ST::decode(ld_hint(reinterpret_cast<const T*>(src + q * qbytes + uint64_t(pull_src<q>(nb))),
+                                      FL & FL_NT_LOAD));
+        });
+        collide_encode<ST, NEWTON, SR, MODEL>(x, out, p, p.node0 + n);
+    }
     const uint32_t nbytes = n * uint32_t(sizeof(T));
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
