@@ -21,6 +21,12 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   run / collide_field             -- per-node conservation, uniform fixed
                                     point, sound speed and decay rates
                                     against linearised Navier-Stokes-Fourier.
+  path_length (entropic step)     -- H(f + alpha (feq - f)) = H(f) with H
+                                    evaluated directly from its definition,
+                                    alpha -> 2 near equilibrium with the
+                                    cubic-order correction, H decrease of the
+                                    post-collision state, the positivity cap,
+                                    a brute-force scan of the sign change.
 """
 import ctypes
 import os
@@ -58,6 +64,8 @@ def _load():
         "orc_collide_node": (i, [_dp, d, _dp]),
         "orc_equilibrium_iso": (i, [d, d, d, d, _dp, _dp, _dp, _ip]),
         "orc_collide_node_model": (i, [_dp, d, i, _dp]),
+        "orc_path_length": (d, [_dp, _dp]),
+        "orc_path_dh": (d, [_dp, _dp, d]),
         "orc_init_model": (i, [i, i, i, _dp, _dp, _dp, _dp, _dp, i, _dp]),
         "orc_collide_field_model": (i, [i, i, i, d, i, _dp, _dp]),
         "orc_run_model": (i, [i, i, i, d, i, _dp, _dp, i]),
@@ -150,12 +158,37 @@ def equilibrium_iso(rho, u):
     return feq, lam, float(res[0]), it.value, rc
 
 
-# equilibrium models: 0 energy conserving (E2), 1 isothermal, 2 series (E1)
+# equilibrium models: 0 energy conserving (E2), 1 isothermal, 2 series (E1);
+# ENTROPIC adds the entropic path length to the relaxation (E2, isothermal)
 MODELS = {"thermal": 0, "isothermal": 1, "series": 2}
+ENTROPIC = 4
 
 
-def _model(model):
-    return MODELS[model] if isinstance(model, str) else int(model)
+def _model(model, entropic=False):
+    m = MODELS[model] if isinstance(model, str) else int(model)
+    if entropic:
+        if m == MODELS["series"]:
+            raise ValueError("the entropic path length needs an exact entropic equilibrium (thermal or isothermal)")
+        m |= ENTROPIC
+    return m
+
+
+def path_length(f, feq):
+    """Entropic path length alpha of one node: the nontrivial root of
+    H(f + a (feq - f)) = H(f) in (1, a_cap] (a_cap = (1 - 2^-10) a_max, a_max
+    the largest a that keeps f + a (feq - f) positive); 2 when f = feq."""
+    f, feq = _f64(f), _f64(feq)
+    if f.size != NQ or feq.size != NQ:
+        raise ValueError("one node of 41 populations expected")
+    return float(_load().orc_path_length(_d(f), _d(feq)))
+
+
+def path_dh(f, feq, a):
+    """H(f + a (feq - f)) - H(f) by the oracle's rewritten form."""
+    f, feq = _f64(f), _f64(feq)
+    if f.size != NQ or feq.size != NQ:
+        raise ValueError("one node of 41 populations expected")
+    return float(_load().orc_path_dh(_d(f), _d(feq), float(a)))
 
 
 def series_rest(rho, eta):
@@ -177,10 +210,12 @@ def equilibrium_series(rho, u, theta):
     return out
 
 
-def collide_node(f, omega, model="thermal"):
+def collide_node(f, omega, model="thermal", entropic=False):
     f = _f64(f)
+    if f.size != NQ:
+        raise ValueError("one node of 41 populations expected")
     out = np.zeros(NQ)
-    rc = _load().orc_collide_node_model(_d(f), float(omega), _model(model), _d(out))
+    rc = _load().orc_collide_node_model(_d(f), float(omega), _model(model, entropic), _d(out))
     if rc != 0:
         raise RuntimeError("oracle equilibrium did not converge")
     return out
@@ -223,20 +258,20 @@ def init(nx, ny, nz, rho, ux, uy, uz, theta, model="thermal"):
     return f
 
 
-def collide_field(nx, ny, nz, omega, f, model="thermal"):
+def collide_field(nx, ny, nz, omega, f, model="thermal", entropic=False):
     f = _pops(f, 2 * nx * ny * nz)
     out = np.zeros_like(f)
-    rc = _load().orc_collide_field_model(nx, ny, nz, float(omega), _model(model), _d(f), _d(out))
+    rc = _load().orc_collide_field_model(nx, ny, nz, float(omega), _model(model, entropic), _d(f), _d(out))
     if rc != 0:
         raise RuntimeError("oracle equilibrium did not converge")
     return out
 
 
-def run(nx, ny, nz, omega, f, nsteps, model="thermal"):
+def run(nx, ny, nz, omega, f, nsteps, model="thermal", entropic=False):
     """Advance populations f [41, N] by nsteps collide+push steps (in place copy returned)."""
     f = _pops(f, 2 * nx * ny * nz, copy=True)
     tmp = np.empty_like(f)
-    rc = _load().orc_run_model(nx, ny, nz, float(omega), _model(model), _d(f), _d(tmp), int(nsteps))
+    rc = _load().orc_run_model(nx, ny, nz, float(omega), _model(model, entropic), _d(f), _d(tmp), int(nsteps))
     if rc != 0:
         raise RuntimeError("oracle equilibrium did not converge during run")
     return f

@@ -418,13 +418,91 @@ void orc_equilibrium_series(double rho, double ux, double uy, double uz, double 
 /* Collision (Sec. II, discrete BGK)                                        */
 /* ------------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------------ */
+/* Entropic path length (Sec. IX.A and IX.D; H-function of Sec. V)          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Entropy change along the line through f and f_eq: with x_i = f_eq,i/f_i - 1
+ * the state f + a (f_eq - f) has components f_i (1 + a x_i), and
+ *   dH(a) = H(f + a (f_eq - f)) - H(f)
+ *         = sum_i f_i (1 + a x_i) log(1 + a x_i) - a sum_i f_i x_i log(1 + x_i),
+ * which follows from H = sum f (log(f/w) - 1) because f_eq - f carries no
+ * mass, momentum or energy and log(f_eq/w) is a combination of 1, c and c^2
+ * (Sec. V). The same expression with f_eq of the isothermal model holds with
+ * 1 and c. p1 = sum_i f_i x_i log(1 + x_i) is passed in.
+ */
+static double path_dh(const double *f, const double *x, double p1, double a)
+{
+    double s = 0.0;
+    for (int i = 0; i < NQ; ++i) {
+        const double y = a * x[i];
+        s += f[i] * ((1.0 + y) * log1p(y) - y);  /* - y: sum_i f_i x_i = 0 */
+    }
+    return s - a * p1;
+}
+
+/*
+ * Path length alpha of the entropic step (Sec. IX.A: alpha = 2 is the
+ * standard BGK step, the entropic method chooses alpha from the H theorem;
+ * Sec. IX.D: computed from x_i = f_eq,i/f_i - 1). Reading: alpha is the
+ * nontrivial root of dH(a) = 0, the mirror state f + alpha (f_eq - f) having
+ * the entropy of f. dH is convex with dH(0) = 0 and its minimum at a = 1
+ * (the equilibrium), so the root lies in (1, a_max), where a_max =
+ * min_{x_i < 0} (-1/x_i) keeps the mirror state positive. The search is
+ * limited to (1, a_cap], a_cap = (1 - 2^-10) a_max; if dH(a_cap) <= 0 the
+ * path length is a_cap. f = f_eq gives alpha = 2. Plain bisection.
+ */
+double orc_path_length(const double *f, const double *feq)
+{
+    double x[NQ], p1 = 0.0, xmin = 0.0;
+    int any = 0;
+    for (int i = 0; i < NQ; ++i) {
+        x[i] = (feq[i] - f[i]) / f[i];
+        p1 += f[i] * x[i] * log1p(x[i]);
+        if (x[i] != 0.0) any = 1;
+        if (x[i] < xmin) xmin = x[i];
+    }
+    if (!any) return 2.0;
+    const double acap = (xmin < 0.0 ? -1.0 / xmin : INFINITY) * (1.0 - 1.0 / 1024.0);
+    double lo = 1.0, hi = acap;
+    if (!(path_dh(f, x, p1, hi) > 0.0)) return hi;
+    for (int it = 0; it < 400; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        if (path_dh(f, x, p1, mid) > 0.0) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* dH(a) of the state f toward feq (as in orc_path_length), for tests. */
+double orc_path_dh(const double *f, const double *feq, double a)
+{
+    double x[NQ], p1 = 0.0;
+    for (int i = 0; i < NQ; ++i) {
+        x[i] = (feq[i] - f[i]) / f[i];
+        p1 += f[i] * x[i] * log1p(x[i]);
+    }
+    return path_dh(f, x, p1, a);
+}
+
+/* Equilibrium models (low two bits): 0 energy conserving (E2), 1 isothermal,
+ * 2 series (E1); ORC_ENTROPIC adds the entropic path length (E2 and
+ * isothermal only). */
+#define ORC_ENTROPIC 4
+
 /* f* = f + omega (f_eq - f) for one node (Sec. II), with the equilibrium of
  * the node's rho, u, theta (model 0, energy conserving, E2), of its rho, u
  * (model 1, isothermal) or the series equilibrium E1 of its rho, u, theta
- * (model 2). */
+ * (model 2). With ORC_ENTROPIC, f* = f + alpha (omega/2) (f_eq - f) with the
+ * path length alpha of the node (Sec. IX.A: alpha beta with beta = omega/2). */
 int orc_collide_node_model(const double *f, double omega, int model, double *out)
 {
     double m[5], feq[NQ];
+    const int entropic = (model & ORC_ENTROPIC) != 0;
+    model &= 3;
+    if (entropic && model == 2) return -2;
     orc_node_moments(f, m);
     double rho = m[0];
     double ux = m[1] / rho, uy = m[2] / rho, uz = m[3] / rho;
@@ -440,7 +518,8 @@ int orc_collide_node_model(const double *f, double omega, int model, double *out
         double theta = (2.0 * m[4] / rho - (ux * ux + uy * uy + uz * uz)) / 3.0;
         rc = orc_equilibrium(rho, ux, uy, uz, theta, feq, NULL, NULL, NULL);
     }
-    for (int i = 0; i < NQ; ++i) out[i] = f[i] + omega * (feq[i] - f[i]);
+    const double om = entropic ? 0.5 * omega * orc_path_length(f, feq) : omega;
+    for (int i = 0; i < NQ; ++i) out[i] = f[i] + om * (feq[i] - f[i]);
     return rc;
 }
 
@@ -533,6 +612,7 @@ int orc_init_model(int nx, int ny, int nz, const double *rho, const double *ux, 
     lattice_build();
     int64_t N = 2LL * nx * ny * nz;
     int bad = 0;
+    model &= 3; /* the initial state is the equilibrium; the path length plays no part */
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int64_t n = 0; n < N; ++n) {
         double feq[NQ];

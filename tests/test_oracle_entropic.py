@@ -1,0 +1,148 @@
+"""Pins for the oracle's entropic path length (Sec. IX.A and IX.D: the
+relaxation f* = f + alpha beta (f_eq - f), alpha = 2 for BGK, chosen by the
+H theorem for the entropic method; H of Sec. V).
+
+Every check here evaluates H directly from its definition
+H = sum f (log(f/w) - 1) in numpy, so a mistake in the oracle's rewritten
+entropy difference or in its root search fails one of them."""
+import numpy as np
+import pytest
+
+
+def H(f, w):
+    return float(np.sum(f * (np.log(f / w) - 1.0)))
+
+
+def _state(orc, seed, amp, model="thermal", u=(0.05, -0.02, 0.03), eta=0.01):
+    """A node away from equilibrium (equilibrium times 1 + U(-amp, amp)) and
+    the equilibrium of its own moments."""
+    c, w, t0 = orc.lattice()
+    rng = np.random.default_rng(seed)
+    if model == "thermal":
+        fe0 = orc.equilibrium(1.0, np.array(u), t0 * (1 + eta))[0]
+    else:
+        fe0 = orc.equilibrium_iso(1.0, np.array(u))[0]
+    f = fe0 * (1.0 + amp * rng.uniform(-1.0, 1.0, 41))
+    m = orc.node_moments(f)
+    rho = m[0]
+    uu = m[1:4] / rho
+    if model == "thermal":
+        th = (2 * m[4] / rho - uu @ uu) / 3
+        feq = orc.equilibrium(rho, uu, th)[0]
+    else:
+        feq = orc.equilibrium_iso(rho, uu)[0]
+    return f, feq, w
+
+
+@pytest.mark.parametrize("model", ["thermal", "isothermal"])
+def test_rewritten_entropy_difference_matches_definition(orc, model):
+    """The oracle's dH(a) (moments of f_eq - f removed analytically) equals
+    H(f + a (f_eq - f)) - H(f) from the definition, for both exact entropic
+    equilibria (energy conserving and isothermal)."""
+    for seed, amp in ((1, 0.05), (2, 0.2), (3, 0.6)):
+        f, feq, w = _state(orc, seed, amp, model)
+        for a in (0.5, 1.0, 1.7, 2.0, 2.3):
+            if not np.all(f + a * (feq - f) > 0):
+                continue
+            direct = H(f + a * (feq - f), w) - H(f, w)
+            assert abs(orc.path_dh(f, feq, a) - direct) <= 1e-9 * abs(direct) + 1e-14
+
+
+@pytest.mark.parametrize("model", ["thermal", "isothermal"])
+def test_path_length_is_the_equal_entropy_root(orc, model):
+    """H of the mirror state f + alpha (f_eq - f) equals H(f), alpha > 1,
+    and the direct entropy difference changes sign at alpha on a fine scan
+    (brute force over a in (1, 4))."""
+    for seed, amp in ((4, 0.05), (5, 0.3), (6, 0.7)):
+        f, feq, w = _state(orc, seed, amp, model)
+        a = orc.path_length(f, feq)
+        scale = float(np.sum(f * ((feq - f) / f) ** 2))
+        assert a > 1.0
+        assert abs(H(f + a * (feq - f), w) - H(f, w)) <= 1e-9 * scale
+        grid = np.linspace(1.0 + 1e-3, 4.0, 3001)
+        x = (feq - f) / f
+        grid = grid[np.all(1 + grid[:, None] * x[None, :] > 0, axis=1)]
+        dh = np.array([H(f + g * (feq - f), w) - H(f, w) for g in grid])
+        k = np.flatnonzero(np.diff(np.sign(dh)) > 0)
+        assert len(k) == 1
+        assert grid[k[0]] - 1e-12 <= a <= grid[k[0] + 1] + 1e-12
+
+
+def test_near_equilibrium_limit_and_cubic_correction(orc):
+    """Expanding dH in x_i = f_eq,i/f_i - 1 gives the root
+    alpha = 2 + S3/(3 S2) + O(x^2) with S_n = sum f x^n: the deviation from
+    2 shrinks linearly with the amplitude, the remainder quadratically."""
+    rem = []
+    for amp in (1e-2, 1e-3):
+        f, feq, w = _state(orc, 7, amp)
+        x = (feq - f) / f
+        s2, s3 = np.sum(f * x ** 2), np.sum(f * x ** 3)
+        a = orc.path_length(f, feq)
+        assert abs(a - 2.0) < 10 * amp
+        rem.append(abs(a - 2.0 - s3 / (3 * s2)))
+    assert rem[1] < rem[0] / 30
+
+
+def test_post_collision_entropy_does_not_grow(orc):
+    """With beta = omega/2 in (0, 1], H(f + alpha beta (f_eq - f)) <= H(f)
+    (convexity along the line: the H theorem of the entropic step)."""
+    for seed in range(8, 14):
+        f, feq, w = _state(orc, seed, 0.4)
+        for omega in (0.5, 1.2, 1.9, 1.999):
+            out = orc.collide_node(f, omega, entropic=True)
+            assert H(out, w) <= H(f, w) + 1e-15
+
+
+def test_positivity_cap(orc):
+    """A population far above its equilibrium: x_min close to -1 puts the
+    positivity limit of the mirror state below the root, so the path length
+    is (1 - 2^-10) a_max and dH there is still negative."""
+    f, feq, w = _state(orc, 15, 0.05)
+    f = f.copy()
+    f[7] *= 40.0
+    m = orc.node_moments(f)
+    uu = m[1:4] / m[0]
+    feq = orc.equilibrium(m[0], uu, (2 * m[4] / m[0] - uu @ uu) / 3)[0]
+    x = (feq - f) / f
+    amax = -1.0 / x.min()
+    a = orc.path_length(f, feq)
+    assert amax < 2.0
+    acap = amax * (1 - 2.0 ** -10)
+    assert H(f + acap * (feq - f), w) - H(f, w) < -0.1
+    assert a == acap
+    assert np.all(f + a * (feq - f) > 0)
+
+
+def test_equilibrium_is_a_fixed_point_and_alpha_two(orc):
+    c, w, t0 = orc.lattice()
+    feq = orc.equilibrium(1.1, np.array([0.03, 0.0, -0.01]), t0 * 0.98)[0]
+    assert orc.path_length(feq, feq) == 2.0
+    out = orc.collide_node(feq, 1.5, entropic=True)
+    assert np.max(np.abs(out - feq)) <= 1e-15
+
+
+@pytest.mark.parametrize("model", ["thermal", "isothermal"])
+def test_entropic_collision_conserves(orc, model):
+    """Any path length keeps the conserved moments: f_eq - f has none."""
+    for seed in range(16, 20):
+        f, feq, w = _state(orc, seed, 0.3, model)
+        out = orc.collide_node(f, 1.7, model=model, entropic=True)
+        m0, m1 = orc.node_moments(f), orc.node_moments(out)
+        k = 5 if model == "thermal" else 4
+        assert np.max(np.abs(m1[:k] - m0[:k])) <= 1e-15 * 10
+
+
+def test_bgk_is_alpha_two(orc):
+    """alpha = 2 reproduces the BGK step (Sec. IX.A)."""
+    f, feq, w = _state(orc, 21, 0.1)
+    a = orc.path_length(f, feq)
+    bgk = orc.collide_node(f, 1.3)
+    ent = orc.collide_node(f, 1.3, entropic=True)
+    np.testing.assert_allclose(ent, f + (a / 2) * 1.3 * (feq - f), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(bgk, f + 1.3 * (feq - f), rtol=0, atol=1e-15)
+
+
+def test_series_model_is_rejected(orc):
+    f, feq, w = _state(orc, 22, 0.1)
+    with pytest.raises(ValueError):
+        orc.collide_node(f, 1.3, model="series", entropic=True)
