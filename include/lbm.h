@@ -89,6 +89,18 @@ typedef enum {
                                            conserved, momentum up to O(u eta^k) terms.
                                            Not with LBM_FLAG_ISOTHERMAL. Default launch
                                            shape, as for the isothermal model. */
+#define LBM_FLAG_ENTROPIC 8u            /* entropic path length (Sec. IX.A: relaxation
+                                           f + alpha beta (f_eq - f), beta = omega/2,
+                                           alpha = 2 for BGK; Sec. IX.D: alpha from
+                                           x_q = f_eq,q/f_q - 1; H of Sec. V): alpha per
+                                           node is the nontrivial root of
+                                           H(f + alpha (f_eq - f)) = H(f) in (1, a_cap],
+                                           a_cap = (1 - 2^-10) min_{x_q<0} (-1/x_q) (the
+                                           mirror state stays positive), a_cap when no root
+                                           lies below it. With the energy-conserving or the
+                                           isothermal equilibrium; not with
+                                           LBM_FLAG_SERIES_EQUILIBRIUM. Default launch
+                                           shape. */
 
 /* Meaning of lbm_box.tau. */
 typedef enum {
@@ -311,7 +323,8 @@ int lbm_selftest(void);
  * or FP32 (precision 1) and `newton` Newton steps: f_out = C[f_in] for one
  * node's 41 populations (direct storage; inputs rounded to the precision).
  * flags: 0, LBM_FLAG_ISOTHERMAL or LBM_FLAG_SERIES_EQUILIBRIUM for the
- * isothermal or the series equilibrium.
+ * isothermal or the series equilibrium, plus LBM_FLAG_ENTROPIC for the
+ * entropic path length (not with the series equilibrium).
  * For testing the arithmetic without a device. Errors: LBM_E_ARG.
  */
 int lbm_collide_host(int32_t precision, int32_t newton, uint32_t flags, double omega, const double *f_in,

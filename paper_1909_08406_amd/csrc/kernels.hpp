@@ -52,10 +52,181 @@ struct CollideConst {
 };
 
 // Equilibrium models: the energy-conserving entropic equilibrium E2, the
-// isothermal one (mass and momentum only) and the series equilibrium E1.
+// isothermal one (mass and momentum only) and the series equilibrium E1 (low
+// two bits). MODEL_ENTROPIC adds the entropic path length to the relaxation
+// (with E2 or the isothermal equilibrium, the exact minimisers of H).
 constexpr int MODEL_E2 = 0;
 constexpr int MODEL_ISO = 1;
 constexpr int MODEL_SERIES = 2;
+constexpr int MODEL_ENTROPIC = 4;
+constexpr int MODEL_BASE_MASK = 3;
+
+// ---------------------------------------------------------------------------
+// Entropic path length (Sec. IX.A: the relaxation f + alpha beta (f_eq - f)
+// with beta = omega/2, where alpha = 2 is the BGK step and the entropic
+// method chooses alpha by the H theorem; Sec. IX.D: alpha from
+// x_q = f_eq,q/f_q - 1; H = sum f (log(f/w) - 1) of Sec. V).
+//
+// alpha is the nontrivial root of dH(a) = H(f + a (f_eq - f)) - H(f), the
+// mirror state having the entropy of f. Because f_eq - f carries no conserved
+// moment and log(f_eq/w) lies in their span,
+//   dH(a) = sum_q f_q [(1 + a x_q) log(1 + a x_q) - a x_q] - a sum_q f_q x_q log(1 + x_q).
+// dH is convex with its minimum at a = 1, so the root lies in (1, a_cap],
+// a_cap = (1 - 2^-10) min_{x_q < 0} (-1/x_q) keeping the mirror state
+// positive; alpha = a_cap when dH(a_cap) <= 0.
+//
+// Near equilibrium (max |x_q| <= XS) dH/a is a power series in x,
+//   dH(a)/a = sum_{n >= 2} (-1)^n S_n (a^{n-1} - n) / (n (n-1)),  S_n = sum_q f_q x_q^n,
+// truncated at order N (the truncated terms move alpha by less than the
+// storage rounding moves f) and solved by Newton from a = 2: one pass over
+// the populations for the S_n, then scalar work only. Farther from
+// equilibrium Newton runs on dH itself (a pass over the populations with
+// log1p per iteration, at most ITMAX iterations).
+// ---------------------------------------------------------------------------
+template <typename R>
+struct PathConst;
+template <>
+struct PathConst<float> {
+    static constexpr int N = 7;
+    static constexpr float XS = 0.0625f;
+    static constexpr int IT = 3;
+    static constexpr int ITMAX = 40;
+    static constexpr float TOL = 1e-6f;
+};
+template <>
+struct PathConst<double> {
+    static constexpr int N = 10;
+    static constexpr double XS = 0.015625;
+    static constexpr int IT = 4;
+    static constexpr int ITMAX = 60;
+    static constexpr double TOL = 1e-14;
+};
+
+// log(1 + y): FP32 from the hardware logarithm with the correction
+// log(u) y / (u - 1), u = 1 + y rounded (accurate for small y as well);
+// FP64 from the math library.
+template <typename R>
+__host__ __device__ inline R d_log1p(R y);
+template <>
+__host__ __device__ inline float d_log1p<float>(float y)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float u = 1.0f + y;
+    return u == 1.0f ? y : __logf(u) * (y * __builtin_amdgcn_rcpf(u - 1.0f));
+#else
+    return std::log1p(y);
+#endif
+}
+template <>
+__host__ __device__ inline double d_log1p<double>(double y)
+{
+    return log1p(y);
+}
+
+// Opaque to the optimiser (no instruction): values recomputed after it are
+// not merged with copies computed before it, which would keep those live.
+template <typename R>
+__host__ __device__ inline void opaque(R& v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+v"(v));
+#else
+    (void)v;
+#endif
+}
+
+// fd(q, f, d) gives f_q and d_q = f_eq,q - f_q of the node; fresh() makes
+// the inputs of fd opaque before the far path recomputes them.
+template <typename R, class FD, class FRESH>
+__host__ __device__ __forceinline__ R path_length(const FD& fd, const FRESH& fresh)
+{
+    using PC = PathConst<R>;
+    constexpr int N = PC::N;
+    R S[N + 1];
+#pragma unroll
+    for (int n = 0; n <= N; ++n) S[n] = R(0);
+    R xabs = R(0), xmin = R(0);
+    static_for<Q>([&](auto qc) {
+        R f, d;
+        fd(qc, f, d);
+        const R x = d * d_rcp<R>(f);
+        xabs = fmax(xabs, fabs(x));
+        xmin = fmin(xmin, x);
+        R t = d * x;  // f x^2
+#pragma unroll
+        for (int n = 2; n <= N; ++n) {
+            S[n] += t;
+            t *= x;
+        }
+    });
+    // the sums are complete here (not sunk into the branch that uses them,
+    // which would keep the 41 x_q live across it)
+#pragma unroll
+    for (int n = 2; n <= N; ++n) opaque(S[n]);
+    opaque(xabs);
+    opaque(xmin);
+    fresh();
+    if (__builtin_expect(!(xabs <= R(PC::XS)), 0)) {
+        // far from equilibrium (rare): Newton on dH itself from
+        // a = min(2, a_cap), over f_q and x_q held in private memory
+        // (volatile: read back in plain loops, not kept in registers)
+        volatile R fb[Q], xb[Q];
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            R f, d;
+            fd(qc, f, d);
+            fb[q] = f;
+            xb[q] = d * d_rcp<R>(f);
+        });
+        const R acap = xmin < R(0) ? (R(1) - R(1.0 / 1024)) * (R(-1) / xmin) : R(1e30);
+        R P = R(0);  // sum_q f_q x_q log(1 + x_q)
+#pragma clang loop unroll(disable)
+        for (int q = 0; q < Q; ++q) {
+            const R f = fb[q], x = xb[q];
+            P = fma(f * x, d_log1p<R>(x), P);
+        }
+        R a = fmin(R(2), acap);
+#pragma clang loop unroll(disable)
+        for (int it = 0; it < PC::ITMAX; ++it) {
+            R g = R(0), gp = R(0);
+#pragma clang loop unroll(disable)
+            for (int q = 0; q < Q; ++q) {
+                const R f = fb[q], x = xb[q];
+                const R y = a * x;
+                const R L = d_log1p<R>(y);
+                g = fma(f, fma(R(1) + y, L, -y), g);
+                gp = fma(f * x, L, gp);
+            }
+            g = fma(-a, P, g);
+            gp -= P;
+            if (!(gp > R(0))) break;
+            const R an = fmin(fmax(a - g / gp, R(1)), acap);
+            const bool done = fabs(an - a) <= R(PC::TOL) * a;
+            a = an;
+            if (done) break;
+        }
+        fresh();
+        return a;
+    }
+    // G(a) = dH(a)/a = sum_n c_n (a^{n-1} - n), c_n = (-1)^n S_n / (n (n-1))
+    R c[N + 1];
+#pragma unroll
+    for (int n = 2; n <= N; ++n) c[n] = ((n & 1) ? -S[n] : S[n]) * R(1.0 / (n * (n - 1)));
+    R a = R(2);
+#pragma unroll
+    for (int it = 0; it < PC::IT; ++it) {
+        R G = R(0), Gp = R(0), p = R(1);  // p = a^{n-2}
+#pragma unroll
+        for (int n = 2; n <= N; ++n) {
+            Gp = fma(c[n] * R(n - 1), p, Gp);
+            G = fma(c[n], fma(a, p, R(-n)), G);
+            p *= a;
+        }
+        if (Gp > R(0)) a -= G / Gp;
+    }
+    if (!(a > R(1) && a < R(4))) a = R(2);  // only where the S_n are rounding noise
+    return a;
+}
 
 // For direct storage in FP64 x is overwritten by the deviations
 // d_q = f_q - w_q (exact while f_q is within a factor two of w_q), so only d
@@ -71,7 +242,7 @@ constexpr bool DEV_IN_PLACE = std::is_same<R, double>::value;
 struct NoReload {};
 
 template <typename R, bool SHIFTED, int NEWTON, int MODEL = MODEL_E2, class XR = NoReload>
-__host__ __device__ inline void collide(R x[Q], R y[Q], const CollideConst<R>& cc, R& rho_out, R& theta_out,
+__host__ __device__ __forceinline__ void collide(R x[Q], R y[Q], const CollideConst<R>& cc, R& rho_out, R& theta_out,
                                         const XR& xr = XR())
 {
     ShellSums<R> SS;
@@ -118,17 +289,22 @@ __host__ __device__ inline void collide(R x[Q], R y[Q], const CollideConst<R>& c
     rho_out = st.rho;
     theta_out = theta;
 
-    const R om = cc.om, om1 = R(1) - om;
+    constexpr int BASE = MODEL & MODEL_BASE_MASK;
+    static_assert(!(MODEL & MODEL_ENTROPIC) || BASE != MODEL_SERIES, "path length needs an exact minimiser of H");
+    R om = cc.om, om1 = R(1) - om;
+    R omw[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) omw[s] = cc.omw[s];
     // f_eq,q - w_q rho_ref = w_q rho_ref D_q; relaxation of population q
     auto relax = [&](auto qc, R D) {
         constexpr int q = decltype(qc)::value;
         constexpr int sh = VEL[q].shell;
-        if constexpr (SHIFTED && !std::is_same<XR, NoReload>::value) y[q] = fma(om1, xr(qc), cc.omw[sh] * D);
-        else if constexpr (SHIFTED) y[q] = fma(om1, x[q], cc.omw[sh] * D);          // h* = (1-w) h + w 2^k d_eq
-        else if constexpr (DEV_IN_PLACE<R>) y[q] = fma(cc.omw[sh], D, -om * x[q]);  // f* - f = w (f_eq - f)
-        else y[q] = fma(cc.omw[sh], D, -om * (x[q] - R(weight(q))));
+        if constexpr (SHIFTED && !std::is_same<XR, NoReload>::value) y[q] = fma(om1, xr(qc), omw[sh] * D);
+        else if constexpr (SHIFTED) y[q] = fma(om1, x[q], omw[sh] * D);          // h* = (1-w) h + w 2^k d_eq
+        else if constexpr (DEV_IN_PLACE<R>) y[q] = fma(omw[sh], D, -om * x[q]);  // f* - f = w (f_eq - f)
+        else y[q] = fma(omw[sh], D, -om * (x[q] - R(weight(q))));
     };
-    if constexpr (MODEL == MODEL_SERIES) {
+    if constexpr (BASE == MODEL_SERIES) {
         // 1 + D_q = (1 + eps_q) rho / (rho_ref sum_i w_i)
         // eta = theta/theta0 - 1 from the deviations of 2E and rho:
         // 3 theta0 rho eta = rho_ref (sum w c^2 - 3 theta0 sum w) + de2 - 3 theta0 drho - rho u^2
@@ -146,7 +322,7 @@ __host__ __device__ inline void collide(R x[Q], R y[Q], const CollideConst<R>& c
         return;
     }
     Mult<R> m;
-    if constexpr (MODEL == MODEL_ISO) {
+    if constexpr (BASE == MODEL_ISO) {
         // isothermal: g = 0, Maxwellian guess at theta0
         m.b[0] = ux * R(1.0 / THETA0);
         m.b[1] = uy * R(1.0 / THETA0);
@@ -167,7 +343,50 @@ __host__ __device__ inline void collide(R x[Q], R y[Q], const CollideConst<R>& c
     // 1 + D_q = (1 + eps_q)(1 + kappa)
     Shells<R> S;
     shells_at<R>(m, S);
-    const R kap = kappa_of<R>(st, S);
+    R kap = kappa_of<R>(st, S);
+    if constexpr ((MODEL & MODEL_ENTROPIC) != 0) {
+        // f_q and f_eq,q - f_q from the stored values
+        auto fd = [&](auto qc, R& f, R& d) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int sh = VEL[q].shell;
+            const R D = dmul(gibbs_dev<q, R>(S), kap);
+            if constexpr (SHIFTED) {
+                const R wr = R(weight(q)) * cc.rho_ref, h = x[q] * cc.inv_scale[sh];
+                f = wr + h;
+                d = fma(wr, D, -h);
+            } else if constexpr (DEV_IN_PLACE<R>) {
+                f = R(weight(q)) + x[q];
+                d = fma(R(weight(q)), D, -x[q]);
+            } else {
+                f = x[q];
+                d = fma(R(weight(q)), D, -(x[q] - R(weight(q))));
+            }
+        };
+        // the relaxation below recomputes D_q and f_q rather than keeping
+        // 41 values of each live
+        auto fresh = [&]() {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                opaque(S.sh[a]);
+                opaque(S.chm[a]);
+                opaque(S.s1[a]);
+                opaque(S.c1m[a]);
+                opaque(S.s2[a]);
+                opaque(S.c2m[a]);
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) opaque(S.tau[k]);
+            opaque(kap);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) opaque(x[q]);
+        };
+        // relaxation rate alpha omega / 2 (alpha = 2: BGK)
+        const R ah = R(0.5) * path_length<R>(fd, fresh);
+        om = cc.om * ah;
+        om1 = R(1) - om;
+#pragma unroll
+        for (int s = 0; s < 6; ++s) omw[s] = cc.omw[s] * ah;
+    }
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         relax(qc, dmul(gibbs_dev<q, R>(S), kap));
@@ -222,7 +441,7 @@ __device__ inline void st_hint(T* p, T v, int nt)
 // flag for an unrealisable node.
 // x: decoded stored values (overwritten by the collision for direct storage).
 template <class ST, int NEWTON, bool SR, int MODEL, class XR = NoReload>
-__device__ inline void collide_encode(typename ST::R x[Q], typename ST::T out[Q], const StepParams& p,
+__device__ __forceinline__ void collide_encode(typename ST::R x[Q], typename ST::T out[Q], const StepParams& p,
                                       uint32_t nid, const XR& xr = XR())
 {
     using R = typename ST::R;
@@ -262,7 +481,7 @@ __device__ inline void collide_encode(typename ST::R x[Q], typename ST::T out[Q]
 // The step of node n of one box: src and dst are the box's first q-block
 // in the current and the other population buffer.
 template <class ST, int NEWTON, int FL, bool SR, int MODEL>
-__device__ inline void step_node(const char* __restrict__ src, char* __restrict__ dst, const StepParams& p,
+__device__ __forceinline__ void step_node(const char* __restrict__ src, char* __restrict__ dst, const StepParams& p,
                                  uint32_t n)
 {
     using R = typename ST::R;
@@ -274,7 +493,7 @@ __device__ inline void step_node(const char* __restrict__ src, char* __restrict_
 
     R x[Q];
     T out[Q];
-    if constexpr (sizeof(T) == 2 && !SR) {
+    if constexpr (sizeof(T) == 2 && !SR && !(MODEL & MODEL_ENTROPIC)) {
         // 16-bit storage, round to nearest: the raw values are also kept two
         // per 32-bit register and decoded again for the relaxation (fewer
         // live registers through the equilibrium solve). Measured faster for
@@ -384,6 +603,7 @@ __device__ inline void equilibrium_dev_f64(double rho, double ux, double uy, dou
     st.j[1] = rho * uy;
     st.j[2] = rho * uz;
     st.de2 = rho * (ux * ux + uy * uy + uz * uz + 3.0 * theta) - rho_ref * SUM_WC2;
+    model &= MODEL_BASE_MASK;  // the path length plays no part in the equilibrium
     if (model == MODEL_SERIES) {
         SeriesCoef<double> sc;
         series_coef<double>(ux, uy, uz, theta / THETA0 - 1.0, sc);

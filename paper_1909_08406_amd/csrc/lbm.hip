@@ -68,6 +68,14 @@ struct Layout {
 // of graph replays at byte COUNTER_OFF.
 constexpr uint64_t COUNTER_OFF = 64;
 
+// Kernel model (equilibrium in the low bits, MODEL_ENTROPIC) of validated flags.
+uint32_t model_of(uint32_t flags)
+{
+    const uint32_t base = (flags & LBM_FLAG_ISOTHERMAL) ? uint32_t(MODEL_ISO)
+                          : (flags & LBM_FLAG_SERIES_EQUILIBRIUM) ? uint32_t(MODEL_SERIES) : uint32_t(MODEL_E2);
+    return base | ((flags & LBM_FLAG_ENTROPIC) ? uint32_t(MODEL_ENTROPIC) : 0u);
+}
+
 int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
 {
     if (!boxes || !opts || nboxes < 1) return LBM_E_ARG;
@@ -75,9 +83,11 @@ int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
     if (eb == 0) return LBM_E_ARG;
     if (opts->tau_conv != LBM_TAU_LB && opts->tau_conv != LBM_TAU_PAPER) return LBM_E_ARG;
     if (opts->newton_iters < 0 || opts->newton_iters > 4) return LBM_E_ARG;
-    if (opts->flags & ~uint32_t(LBM_FLAG_STOCHASTIC_ROUNDING | LBM_FLAG_ISOTHERMAL | LBM_FLAG_SERIES_EQUILIBRIUM))
+    if (opts->flags & ~uint32_t(LBM_FLAG_STOCHASTIC_ROUNDING | LBM_FLAG_ISOTHERMAL | LBM_FLAG_SERIES_EQUILIBRIUM |
+                                LBM_FLAG_ENTROPIC))
         return LBM_E_ARG;
     if ((opts->flags & LBM_FLAG_ISOTHERMAL) && (opts->flags & LBM_FLAG_SERIES_EQUILIBRIUM)) return LBM_E_ARG;
+    if ((opts->flags & LBM_FLAG_ENTROPIC) && (opts->flags & LBM_FLAG_SERIES_EQUILIBRIUM)) return LBM_E_ARG;
     if ((opts->flags & LBM_FLAG_STOCHASTIC_ROUNDING) &&
         !(opts->storage == LBM_F32 || opts->storage == LBM_F16_SHIFT || opts->storage == LBM_BF16_SHIFT))
         return LBM_E_ARG;
@@ -283,11 +293,20 @@ int enqueue_step(lbm_ctx* ctx, int from, uint32_t step, const uint32_t* step_bas
             auto go = [&](auto sr) -> int {
                 using std::integral_constant;
                 if (ctx->base.model != MODEL_E2) {
-                    // the isothermal and series models run the default launch shape
+                    // the other models run the default launch shape
                     const integral_constant<int, 256> blk;
                     const integral_constant<int, 0> fl;
-                    if (ctx->base.model == MODEL_ISO) launch(sr, integral_constant<int, MODEL_ISO>{}, blk, fl);
-                    else launch(sr, integral_constant<int, MODEL_SERIES>{}, blk, fl);
+                    switch (ctx->base.model) {
+                        case MODEL_ISO: launch(sr, integral_constant<int, MODEL_ISO>{}, blk, fl); break;
+                        case MODEL_SERIES: launch(sr, integral_constant<int, MODEL_SERIES>{}, blk, fl); break;
+                        case MODEL_E2 | MODEL_ENTROPIC:
+                            launch(sr, integral_constant<int, MODEL_E2 | MODEL_ENTROPIC>{}, blk, fl);
+                            break;
+                        case MODEL_ISO | MODEL_ENTROPIC:
+                            launch(sr, integral_constant<int, MODEL_ISO | MODEL_ENTROPIC>{}, blk, fl);
+                            break;
+                        default: return LBM_E_ARG;
+                    }
                     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
                 }
                 return with_variant(ctx->variant, [&](auto blk, auto fl) {
@@ -431,9 +450,15 @@ void collide_host(double omega, int model, const double* in, double* out)
     }
     R x[Q], y[Q], rho, theta;
     for (int q = 0; q < Q; ++q) x[q] = R(in[q]);
-    if (model == MODEL_ISO) collide<R, false, NEWTON, MODEL_ISO>(x, y, cc, rho, theta);
-    else if (model == MODEL_SERIES) collide<R, false, NEWTON, MODEL_SERIES>(x, y, cc, rho, theta);
-    else collide<R, false, NEWTON, MODEL_E2>(x, y, cc, rho, theta);
+    switch (model) {
+        case MODEL_ISO: collide<R, false, NEWTON, MODEL_ISO>(x, y, cc, rho, theta); break;
+        case MODEL_SERIES: collide<R, false, NEWTON, MODEL_SERIES>(x, y, cc, rho, theta); break;
+        case MODEL_E2 | MODEL_ENTROPIC: collide<R, false, NEWTON, MODEL_E2 | MODEL_ENTROPIC>(x, y, cc, rho, theta); break;
+        case MODEL_ISO | MODEL_ENTROPIC:
+            collide<R, false, NEWTON, MODEL_ISO | MODEL_ENTROPIC>(x, y, cc, rho, theta);
+            break;
+        default: collide<R, false, NEWTON, MODEL_E2>(x, y, cc, rho, theta); break;
+    }
     for (int q = 0; q < Q; ++q)
         out[q] = DEV_IN_PLACE<R> ? double(R((x[q] + R(SHELL_W[VEL[q].shell])) + y[q]))  // x holds f - w
                                  : double(R(x[q] + y[q]));
@@ -544,8 +569,7 @@ static int init_impl(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const 
 
     ctx->base.flag = ctx->flag;
     ctx->base.xcd_remap = 1;
-    ctx->base.model = (opts->flags & LBM_FLAG_ISOTHERMAL) ? uint32_t(MODEL_ISO)
-                      : (opts->flags & LBM_FLAG_SERIES_EQUILIBRIUM) ? uint32_t(MODEL_SERIES) : uint32_t(MODEL_E2);
+    ctx->base.model = model_of(opts->flags);
     ctx->base.seed = opts->seed;
     ctx->base.rho_ref = shifted ? ctx->rho0 : 0.0;
     ctx->rho_ref_storage = ctx->base.rho_ref;
@@ -853,9 +877,11 @@ int lbm_get_info(lbm_ctx* ctx, lbm_info* info)
     info->storage = ctx->storage;
     info->newton_iters = ctx->newton;
     info->shift_exp = (ctx->storage == LBM_F16_SHIFT || ctx->storage == LBM_BF16_SHIFT) ? ctx->kamp : 0;
+    const uint32_t base = ctx->base.model & MODEL_BASE_MASK;
     info->flags = (ctx->stochastic ? LBM_FLAG_STOCHASTIC_ROUNDING : 0u) |
-                  (ctx->base.model == MODEL_ISO ? LBM_FLAG_ISOTHERMAL : 0u) |
-                  (ctx->base.model == MODEL_SERIES ? LBM_FLAG_SERIES_EQUILIBRIUM : 0u);
+                  (base == MODEL_ISO ? LBM_FLAG_ISOTHERMAL : 0u) |
+                  (base == MODEL_SERIES ? LBM_FLAG_SERIES_EQUILIBRIUM : 0u) |
+                  ((ctx->base.model & MODEL_ENTROPIC) ? LBM_FLAG_ENTROPIC : 0u);
     info->steps_done = ctx->steps_done;
     info->nboxes = int32_t(ctx->boxes.size());
     info->nodes = int64_t(ctx->L.elems / Q);
@@ -987,11 +1013,11 @@ int lbm_collide_host(int32_t precision, int32_t newton, uint32_t flags, double o
                      double* f_out)
 {
     if (!f_in || !f_out || (precision != 0 && precision != 1) || newton < 0 || newton > 4 ||
-        (flags & ~uint32_t(LBM_FLAG_ISOTHERMAL | LBM_FLAG_SERIES_EQUILIBRIUM)) ||
-        ((flags & LBM_FLAG_ISOTHERMAL) && (flags & LBM_FLAG_SERIES_EQUILIBRIUM)))
+        (flags & ~uint32_t(LBM_FLAG_ISOTHERMAL | LBM_FLAG_SERIES_EQUILIBRIUM | LBM_FLAG_ENTROPIC)) ||
+        ((flags & LBM_FLAG_ISOTHERMAL) && (flags & LBM_FLAG_SERIES_EQUILIBRIUM)) ||
+        ((flags & LBM_FLAG_ENTROPIC) && (flags & LBM_FLAG_SERIES_EQUILIBRIUM)))
         return LBM_E_ARG;
-    const int iso = (flags & LBM_FLAG_ISOTHERMAL) ? MODEL_ISO : (flags & LBM_FLAG_SERIES_EQUILIBRIUM) ? MODEL_SERIES
-                                                                                                      : MODEL_E2;
+    const int iso = int(model_of(flags));
     if (precision == 0) {
         switch (newton) {
             case 0: collide_host<double, 0>(omega, iso, f_in, f_out); break;

@@ -18,6 +18,7 @@ F64, F32, F16_SHIFT, BF16_SHIFT, F32_SHIFT = 0, 1, 2, 3, 4
 FLAG_STOCHASTIC_ROUNDING = 1
 FLAG_ISOTHERMAL = 2
 FLAG_SERIES_EQUILIBRIUM = 4
+FLAG_ENTROPIC = 8
 TAU_LB, TAU_PAPER = 0, 1
 SHIFT_AUTO = -1000
 STORAGE = {"f64": F64, "f32": F32, "f16s": F16_SHIFT, "bf16s": BF16_SHIFT, "f32s": F32_SHIFT}
@@ -143,18 +144,19 @@ def _boxes(boxes):
     return arr
 
 
-def _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic=False, seed=0, isothermal=False, series=False):
+def _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic=False, seed=0, isothermal=False, series=False,
+          entropic=False):
     st = STORAGE[storage] if isinstance(storage, str) else int(storage)
     flags = ((FLAG_STOCHASTIC_ROUNDING if stochastic else 0) | (FLAG_ISOTHERMAL if isothermal else 0)
-             | (FLAG_SERIES_EQUILIBRIUM if series else 0))
+             | (FLAG_SERIES_EQUILIBRIUM if series else 0) | (FLAG_ENTROPIC if entropic else 0))
     return Opts(st, int(tau_conv), float(rho0), int(newton_iters),
                 SHIFT_AUTO if shift_exp is None else int(shift_exp), flags, int(seed) & 0xffffffff)
 
 
 def workspace_size(boxes, storage="f32", tau_conv=TAU_LB, rho0=1.0, newton_iters=0, shift_exp=None,
-                   stochastic=False, isothermal=False, series=False):
+                   stochastic=False, isothermal=False, series=False, entropic=False):
     bx = _boxes(boxes)
-    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, 0, isothermal, series)
+    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, 0, isothermal, series, entropic)
     out = ctypes.c_uint64(0)
     _check(lib().lbm_workspace_size(bx, len(boxes), ctypes.byref(op), ctypes.byref(out)), "lbm_workspace_size")
     return int(out.value)
@@ -296,14 +298,14 @@ class Context:
 
 def init(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0, newton_iters=0,
          shift_exp=None, stream=None, torch_workspace=True, stochastic=False, seed=0, isothermal=False,
-         series=False):
+         series=False, entropic=False):
     """lbm_init. boxes: [(nx, ny, nz, tau), ...]; nodal FP64 fields of all
     boxes concatenated (theta absolute; not used by the isothermal model).
     stream: a torch.cuda.Stream (or None for the library's own). With
     torch_workspace the device memory is a torch uint8 tensor held by the
     returned Context."""
     bx = _boxes(boxes)
-    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, seed, isothermal, series)
+    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, seed, isothermal, series, entropic)
     arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (rho, ux, uy, uz, theta)]
     nodes = sum(2 * b[0] * b[1] * b[2] for b in boxes)
     for a in arrs:
@@ -314,7 +316,7 @@ def init(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0
     if torch_workspace:
         import torch
         ws_bytes = workspace_size(boxes, storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, isothermal,
-                                  series)
+                                  series, entropic)
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
         ws_ptr = ws.data_ptr()
     sptr = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
@@ -326,13 +328,14 @@ def init(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0
 
 
 def init_device(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0, newton_iters=0,
-                shift_exp=None, stream=None, stochastic=False, seed=0, isothermal=False, series=False):
+                shift_exp=None, stream=None, stochastic=False, seed=0, isothermal=False, series=False,
+                entropic=False):
     """lbm_init_device: the five fields are contiguous float64 torch CUDA
     tensors (all boxes concatenated); the equilibrium is built from them on
     the device. The workspace is a torch uint8 tensor held by the Context."""
     import torch
     bx = _boxes(boxes)
-    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, seed, isothermal, series)
+    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, seed, isothermal, series, entropic)
     nodes = sum(2 * b[0] * b[1] * b[2] for b in boxes)
     fields = (rho, ux, uy, uz, theta)
     for a in fields:
@@ -340,7 +343,8 @@ def init_device(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, r
             raise TypeError("init_device takes contiguous float64 CUDA tensors")
         if a.numel() != nodes:
             raise ValueError("field has %d values, boxes have %d nodes" % (a.numel(), nodes))
-    ws_bytes = workspace_size(boxes, storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, isothermal, series)
+    ws_bytes = workspace_size(boxes, storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, isothermal, series,
+                              entropic)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     sptr = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
     if stream is not None:
@@ -357,13 +361,14 @@ def selftest():
     return int(lib().lbm_selftest())
 
 
-def collide_host(f, omega, precision="f32", newton=None, isothermal=False, series=False):
+def collide_host(f, omega, precision="f32", newton=None, isothermal=False, series=False, entropic=False):
     """The kernel's per-node collision run on the host (FP64 or FP32)."""
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(NQ)
     out = np.zeros(NQ)
     pr = {"f64": 0, "f32": 1}[precision]
     nt = (3 if pr == 0 else 1) if newton is None else int(newton)
-    flags = (FLAG_ISOTHERMAL if isothermal else 0) | (FLAG_SERIES_EQUILIBRIUM if series else 0)
+    flags = ((FLAG_ISOTHERMAL if isothermal else 0) | (FLAG_SERIES_EQUILIBRIUM if series else 0)
+             | (FLAG_ENTROPIC if entropic else 0))
     _check(lib().lbm_collide_host(pr, nt, flags, float(omega), _d(f), _d(out)),
            "lbm_collide_host")
     return out

@@ -85,6 +85,20 @@ def taylor_green(n, u0):
     return Fields(n, n, n, rho, ux, uy, uz, th)
 
 
+def kida_peltz(n, u0):
+    """Kida-Peltz initial field (the periodic decaying-turbulence case):
+    u_x = u0 sin X (cos 3Y cos Z - cos Y cos 3Z) and its cyclic permutations
+    in (X, Y, Z) = 2 pi (x, y, z)/n at the node positions; rho = 1,
+    theta = theta0."""
+    rho, ux, uy, uz, th = _rest(n, n, n)
+    x, y, z = positions(n, n, n)
+    X, Y, Z = (2.0 * np.pi * v / n for v in (x, y, z))
+    ux = u0 * np.sin(X) * (np.cos(3 * Y) * np.cos(Z) - np.cos(Y) * np.cos(3 * Z))
+    uy = u0 * np.sin(Y) * (np.cos(3 * Z) * np.cos(X) - np.cos(Z) * np.cos(3 * X))
+    uz = u0 * np.sin(Z) * (np.cos(3 * X) * np.cos(Y) - np.cos(X) * np.cos(3 * Y))
+    return Fields(n, n, n, rho, ux, uy, uz, th)
+
+
 def gaussian_pulse(nx, ny=None, nz=None, eps=1e-3, b=8.0):
     """rho = 1 + eps exp(-ln2 r^2 / b^2) (b = half width at half maximum)
     centred on the cell corner (nx/2, ny/2, nz/2), r by periodic minimum

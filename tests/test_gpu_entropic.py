@@ -1,0 +1,129 @@
+"""The entropic path length on the GPU (LBM_FLAG_ENTROPIC; Sec. IX.A: the
+relaxation f + alpha beta (f_eq - f), alpha = 2 for BGK, the entropic
+method choosing alpha by the H theorem; Sec. IX.D). Parity against the
+oracle's path length (bisection on the equal-entropy condition) from states
+far from equilibrium, launch-path identity, and closeness to BGK where the
+flow is resolved."""
+import numpy as np
+import pytest
+
+from paper_1909_08406_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    from paper_1909_08406_amd import lbm
+    return lbm
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _perturbed(orc, dims, seed, amp, model, field=1.0):
+    """Equilibrium of a random state (velocity 0.05 field, density and
+    temperature 0.01 field), each population times 1 + U(-amp, amp): every
+    node starts away from equilibrium by about amp, and the streaming of the
+    random field adds its own departure."""
+    F = wl.random_state(*dims, seed=seed, amp_u=0.05 * field, amp_rho=0.01 * field, amp_theta=0.01 * field)
+    _, _, th = orc.lattice()
+    f = orc.init(*dims, *F.absolute(th), model=model)
+    rng = np.random.default_rng(seed + 1000)
+    return F, f * (1 + amp * rng.uniform(-1, 1, f.shape))
+
+
+@pytest.mark.parametrize("storage,model,amp,field,tol", [
+    ("f64", "thermal", 1e-3, 1.0, 1e-12), ("f64", "thermal", 0.2, 1.0, 1e-12), ("f64", "isothermal", 0.2, 1.0, 1e-12),
+    ("f64", "thermal", 1e-3, 0.02, 1e-12),
+    ("f32", "thermal", 1e-3, 1.0, 1e-5), ("f32", "thermal", 0.2, 1.0, 1e-5), ("f32", "isothermal", 0.2, 1.0, 1e-5),
+    ("f32", "thermal", 1e-3, 0.02, 1e-5), ("f16s", "thermal", 1e-3, 0.02, 1e-5)])
+def test_entropic_vs_oracle_far_from_equilibrium(L, orc, storage, model, amp, field, tol):
+    """Ragged 13x7x5 box loaded with perturbed populations, 6 entropic steps
+    at tau 0.505: amp 0.2 puts most nodes on the kernel's Newton-on-dH path;
+    amp 1e-3 on a 0.02-scaled field keeps every node on its series path
+    (FP16-shifted storage resolves deviations of that size). The GPU holds
+    post-collision values, so the oracle reproduces its sequence: stream (a
+    step with omega = 0), 5 steps, then a collision. Moments normwise
+    (1e-12 FP64, 1e-5 FP32 arithmetic) and populations within 10x that."""
+    dims, tau, steps = (13, 7, 5), 0.505, 6
+    iso = model == "isothermal"
+    F, f0 = _perturbed(orc, dims, 31, amp, model, field)
+    _, _, th = L.lattice()
+    say("entropic %s %s amp %g field %g" % (storage, model, amp, field))
+    ctx = L.init([(*dims, tau)], *F.absolute(th), storage=storage, isothermal=iso, entropic=True)
+    assert ctx.info()["flags"] & L.FLAG_ENTROPIC
+    ctx.set_populations(f0)
+    ctx.step(steps)
+    g = ctx.get_populations().reshape(41, -1)
+    m = ctx.moments()
+    assert ctx.status() == 0
+    ctx.free()
+    f = orc.run(*dims, 0.0, f0, 1, model=model)
+    f = orc.run(*dims, 1 / tau, f, steps - 1, model=model, entropic=True)
+    gref = orc.collide_field(*dims, 1 / tau, f, model=model, entropic=True)
+    m_ref = orc.moment_fields(gref)
+    k = 4 if iso else 5
+    err = float(np.max(np.abs(m[:k] - m_ref[:k])) / np.max(np.abs(m_ref[:k])))
+    perr = float(np.max(np.abs(g - gref)) / np.max(np.abs(gref)))
+    # and the path length made a difference: BGK from the same start differs
+    fb = orc.run(*dims, 1 / tau, orc.run(*dims, 0.0, f0, 1, model=model), steps - 1, model=model)
+    bgk = orc.collide_field(*dims, 1 / tau, fb, model=model)
+    diff = float(np.max(np.abs(bgk - gref)) / np.max(np.abs(gref)))
+    say("  moment error %.2e, population error %.2e (BGK differs by %.2e)" % (err, perr, diff))
+    assert err <= tol and perr <= 10 * tol
+    if amp >= 0.1:
+        assert diff > 100 * perr
+
+
+def test_entropic_batched_and_graph_match_per_box(L):
+    """Three uneven boxes, FP32 with stochastic rounding: the batched
+    schedule and graph replays give bit-identical populations to per-box
+    launches."""
+    boxes = [(12, 8, 6, 0.52), (9, 7, 5, 0.7), (16, 6, 4, 0.505)]
+    _, _, th = L.lattice()
+    fields = [wl.random_state(b[0], b[1], b[2], seed=40 + i, amp_u=0.1) for i, b in enumerate(boxes)]
+    args = wl.concat(fields)
+    out = {}
+    for name, tune in (("per_box", dict(schedule=L.SCHEDULES["per_box"], graph_steps=0)),
+                       ("batched", dict(schedule=L.SCHEDULES["batched"], graph_steps=0)),
+                       ("graph", dict(schedule=L.SCHEDULES["batched"], graph_steps=4))):
+        ctx = L.init(boxes, args[0], args[1], args[2], args[3], args[4] * th, storage="f32", stochastic=True,
+                     entropic=True)
+        ctx.set_tuning(**tune)
+        ctx.step(10)
+        out[name] = ctx.get_populations()
+        assert ctx.status() == 0
+        ctx.free()
+    assert np.array_equal(out["per_box"], out["batched"])
+    assert np.array_equal(out["per_box"], out["graph"])
+
+
+@pytest.mark.parametrize("storage,sr,tol", [("f64", False, 1e-7), ("f32", True, 1e-5), ("f16s", True, 1e-5)])
+def test_entropic_close_to_bgk_on_resolved_flow(L, storage, sr, tol):
+    """Standing wave 32x16x16 at amplitude A = 1e-3, tau 0.6, 200 steps. The
+    departure from equilibrium is x ~ 1e-4 here and alpha = 2 + O(x), so the
+    entropic step changes the effective viscosity by O(x) relative and the
+    field by O(x) of A over a decay time: normwise 1e-7 in FP64 (measured
+    ~6e-9), and within the rounding of the reduced-precision forms."""
+    nx, ny, nz, tau = 32, 16, 16, 0.6
+    _, _, th = L.lattice()
+    F = wl.standing_wave(nx, ny, nz, 1e-3)
+    res = {}
+    for ent in (False, True):
+        ctx = L.init([(nx, ny, nz, tau)], *F.absolute(th), storage=storage, stochastic=sr, entropic=ent)
+        ctx.step(200)
+        res[ent] = ctx.moments()
+        assert ctx.status() == 0
+        ctx.free()
+    d = res[True] - res[False]
+    err = float(np.max(np.abs(d)) / np.max(np.abs(res[False])))
+    drho = float(np.max(np.abs(d[0])) / 1e-3)
+    say("entropic vs BGK %s: %.2e normwise, %.2e of the wave amplitude" % (storage, err, drho))
+    assert err <= tol
+    if storage == "f64":
+        assert drho <= 1e-4
