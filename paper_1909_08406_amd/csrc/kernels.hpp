@@ -79,7 +79,11 @@ constexpr int MODEL_BASE_MASK = 3;
 //   dH(a)/a = sum_{n >= 2} (-1)^n S_n (a^{n-1} - n) / (n (n-1)),  S_n = sum_q f_q x_q^n,
 // truncated at order N (the truncated terms move alpha by less than the
 // storage rounding moves f) and solved by Newton from a = 2: one pass over
-// the populations for the S_n, then scalar work only. Farther from
+// the populations for the S_n, then scalar work only. For 16-bit storage
+// (COARSE) the root of the series to second order in x,
+//   alpha = 2 + (S3 - 2 S4) / (3 S2 - 4 S3),
+// is used for max |x_q| <= 1/32: its error in alpha is O(x^3), moving f* by
+// at most ~3e-6 of f there, below the 16-bit storage quantum. Farther from
 // equilibrium Newton runs on dH itself (a pass over the populations with
 // log1p per iteration, at most ITMAX iterations).
 // ---------------------------------------------------------------------------
@@ -89,6 +93,7 @@ template <>
 struct PathConst<float> {
     static constexpr int N = 7;
     static constexpr float XS = 0.0625f;
+    static constexpr float XS_COARSE = 0.03125f;
     static constexpr int IT = 3;
     static constexpr int ITMAX = 40;
     static constexpr float TOL = 1e-6f;
@@ -97,6 +102,7 @@ template <>
 struct PathConst<double> {
     static constexpr int N = 10;
     static constexpr double XS = 0.015625;
+    static constexpr double XS_COARSE = 0.015625;
     static constexpr int IT = 4;
     static constexpr int ITMAX = 60;
     static constexpr double TOL = 1e-14;
@@ -137,21 +143,21 @@ __host__ __device__ inline void opaque(R& v)
 
 // fd(q, f, d) gives f_q and d_q = f_eq,q - f_q of the node; fresh() makes
 // the inputs of fd opaque before the far path recomputes them.
-template <typename R, class FD, class FRESH>
+template <typename R, bool COARSE, class FD, class FRESH>
 __host__ __device__ __forceinline__ R path_length(const FD& fd, const FRESH& fresh)
 {
     using PC = PathConst<R>;
-    constexpr int N = PC::N;
+    constexpr int N = COARSE ? 4 : PC::N;
+    constexpr R XS = COARSE ? PC::XS_COARSE : PC::XS;
     R S[N + 1];
 #pragma unroll
     for (int n = 0; n <= N; ++n) S[n] = R(0);
-    R xabs = R(0), xmin = R(0);
+    R xabs = R(0);
     static_for<Q>([&](auto qc) {
         R f, d;
         fd(qc, f, d);
         const R x = d * d_rcp<R>(f);
         xabs = fmax(xabs, fabs(x));
-        xmin = fmin(xmin, x);
         R t = d * x;  // f x^2
 #pragma unroll
         for (int n = 2; n <= N; ++n) {
@@ -164,19 +170,21 @@ __host__ __device__ __forceinline__ R path_length(const FD& fd, const FRESH& fre
 #pragma unroll
     for (int n = 2; n <= N; ++n) opaque(S[n]);
     opaque(xabs);
-    opaque(xmin);
     fresh();
-    if (__builtin_expect(!(xabs <= R(PC::XS)), 0)) {
+    if (__builtin_expect(!(xabs <= XS), 0)) {
         // far from equilibrium (rare): Newton on dH itself from
         // a = min(2, a_cap), over f_q and x_q held in private memory
         // (volatile: read back in plain loops, not kept in registers)
         volatile R fb[Q], xb[Q];
+        R xmin = R(0);
         static_for<Q>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             R f, d;
             fd(qc, f, d);
+            const R x = d * d_rcp<R>(f);
             fb[q] = f;
-            xb[q] = d * d_rcp<R>(f);
+            xb[q] = x;
+            xmin = fmin(xmin, x);
         });
         const R acap = xmin < R(0) ? (R(1) - R(1.0 / 1024)) * (R(-1) / xmin) : R(1e30);
         R P = R(0);  // sum_q f_q x_q log(1 + x_q)
@@ -207,6 +215,11 @@ __host__ __device__ __forceinline__ R path_length(const FD& fd, const FRESH& fre
         }
         fresh();
         return a;
+    }
+    if constexpr (COARSE) {
+        const R den = R(3) * S[2] - R(4) * S[3];
+        const R a = R(2) + (S[3] - R(2) * S[4]) / den;
+        return (den > R(0) && a > R(1) && a < R(4)) ? a : R(2);
     }
     // G(a) = dH(a)/a = sum_n c_n (a^{n-1} - n), c_n = (-1)^n S_n / (n (n-1))
     R c[N + 1];
@@ -241,7 +254,7 @@ constexpr bool DEV_IN_PLACE = std::is_same<R, double>::value;
 // the decoded x need not stay live through the equilibrium solve.
 struct NoReload {};
 
-template <typename R, bool SHIFTED, int NEWTON, int MODEL = MODEL_E2, class XR = NoReload>
+template <typename R, bool SHIFTED, int NEWTON, int MODEL = MODEL_E2, class XR = NoReload, bool COARSE = false>
 __host__ __device__ __forceinline__ void collide(R x[Q], R y[Q], const CollideConst<R>& cc, R& rho_out, R& theta_out,
                                         const XR& xr = XR())
 {
@@ -344,12 +357,17 @@ __host__ __device__ __forceinline__ void collide(R x[Q], R y[Q], const CollideCo
     Shells<R> S;
     shells_at<R>(m, S);
     R kap = kappa_of<R>(st, S);
+    // Entropic step in FP32 arithmetic: D_q is kept in y[q] from the path
+    // length's pass to the relaxation (fits the occupancy the kernel has
+    // anyway); in FP64 it is recomputed (keeping it would halve occupancy).
+    constexpr bool KEEP_D = (MODEL & MODEL_ENTROPIC) != 0 && !std::is_same<R, double>::value;
     if constexpr ((MODEL & MODEL_ENTROPIC) != 0) {
         // f_q and f_eq,q - f_q from the stored values
         auto fd = [&](auto qc, R& f, R& d) {
             constexpr int q = decltype(qc)::value;
             constexpr int sh = VEL[q].shell;
             const R D = dmul(gibbs_dev<q, R>(S), kap);
+            if constexpr (KEEP_D) y[q] = D;
             if constexpr (SHIFTED) {
                 const R wr = R(weight(q)) * cc.rho_ref, h = x[q] * cc.inv_scale[sh];
                 f = wr + h;
@@ -362,8 +380,8 @@ __host__ __device__ __forceinline__ void collide(R x[Q], R y[Q], const CollideCo
                 d = fma(R(weight(q)), D, -(x[q] - R(weight(q))));
             }
         };
-        // the relaxation below recomputes D_q and f_q rather than keeping
-        // 41 values of each live
+        // the relaxation and the far path recompute what they need rather
+        // than keeping further values live
         auto fresh = [&]() {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -381,7 +399,7 @@ __host__ __device__ __forceinline__ void collide(R x[Q], R y[Q], const CollideCo
             for (int q = 0; q < Q; ++q) opaque(x[q]);
         };
         // relaxation rate alpha omega / 2 (alpha = 2: BGK)
-        const R ah = R(0.5) * path_length<R>(fd, fresh);
+        const R ah = R(0.5) * path_length<R, COARSE>(fd, fresh);
         om = cc.om * ah;
         om1 = R(1) - om;
 #pragma unroll
@@ -389,7 +407,8 @@ __host__ __device__ __forceinline__ void collide(R x[Q], R y[Q], const CollideCo
     }
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        relax(qc, dmul(gibbs_dev<q, R>(S), kap));
+        if constexpr (KEEP_D) relax(qc, y[q]);
+        else relax(qc, dmul(gibbs_dev<q, R>(S), kap));
     });
 }
 
@@ -454,7 +473,8 @@ __device__ __forceinline__ void collide_encode(typename ST::R x[Q], typename ST:
         cc.omw[s] = ST::shifted ? R(p.omw[s]) : cc.om * R(SHELL_W[s]);
     }
     R y[Q], rho, theta;
-    collide<R, ST::shifted, NEWTON, MODEL>(x, y, cc, rho, theta, xr);
+    // 16-bit storage: the path length to its own resolution
+    collide<R, ST::shifted, NEWTON, MODEL, XR, sizeof(typename ST::T) == 2>(x, y, cc, rho, theta, xr);
     flag_bad<R>(p, rho, theta);
     uint32_t rs = 0, rw = 0;
     if constexpr (SR) {

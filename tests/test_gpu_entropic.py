@@ -41,12 +41,15 @@ def _perturbed(orc, dims, seed, amp, model, field=1.0):
     ("f64", "thermal", 1e-3, 1.0, 1e-12), ("f64", "thermal", 0.2, 1.0, 1e-12), ("f64", "isothermal", 0.2, 1.0, 1e-12),
     ("f64", "thermal", 1e-3, 0.02, 1e-12),
     ("f32", "thermal", 1e-3, 1.0, 1e-5), ("f32", "thermal", 0.2, 1.0, 1e-5), ("f32", "isothermal", 0.2, 1.0, 1e-5),
-    ("f32", "thermal", 1e-3, 0.02, 1e-5), ("f16s", "thermal", 1e-3, 0.02, 1e-5)])
+    ("f32", "thermal", 1e-3, 0.02, 1e-5), ("f16s", "thermal", 1e-3, 0.02, 1e-5),
+    ("f16s", "thermal", 0.02, 0.02, 3e-5)])
 def test_entropic_vs_oracle_far_from_equilibrium(L, orc, storage, model, amp, field, tol):
     """Ragged 13x7x5 box loaded with perturbed populations, 6 entropic steps
     at tau 0.505: amp 0.2 puts most nodes on the kernel's Newton-on-dH path;
     amp 1e-3 on a 0.02-scaled field keeps every node on its series path
-    (FP16-shifted storage resolves deviations of that size). The GPU holds
+    (FP16-shifted storage resolves deviations of that size; at amp 0.02
+    its second-order closed form decides alpha, and the bar is three FP16
+    quanta of the deviation, 3e-5). The GPU holds
     post-collision values, so the oracle reproduces its sequence: stream (a
     step with omega = 0), 5 steps, then a collision. Moments normwise
     (1e-12 FP64, 1e-5 FP32 arithmetic) and populations within 10x that."""
@@ -127,3 +130,42 @@ def test_entropic_close_to_bgk_on_resolved_flow(L, storage, sr, tol):
     assert err <= tol
     if storage == "f64":
         assert drho <= 1e-4
+
+
+def test_entropic_keeps_underresolved_kida_peltz_stable(L):
+    """Kida-Peltz flow (Sec. X.A) on 32^3 cells at Ma 0.3 (U0 = 0.3
+    sqrt(gamma theta0)) and tau 0.5001: a viscosity of 3e-5 that 32 cells
+    cannot resolve. The BGK step loses realisability (non-positive density
+    or temperature flagged) within 1000 steps; the entropic step runs 2000
+    steps with mass and energy kept to FP32 rounding (1e-5 relative), the
+    net momentum at zero, and the kinetic energy below its start."""
+    n, tau = 32, 0.5001
+    _, _, th = L.lattice()
+    F = wl.kida_peltz(n, 0.3 * np.sqrt(5.0 / 3.0 * th))
+    ctx = L.init([(n, n, n, tau)], *F.absolute(th), storage="f32")
+    died = None
+    for s in range(0, 1000, 100):
+        ctx.step(100)
+        if ctx.status() != 0:
+            died = s + 100
+            break
+    ctx.free()
+    say("BGK: %s" % ("lost realisability by step %d" % died if died else "alive at 1000"))
+    assert died is not None
+
+    ctx = L.init([(n, n, n, tau)], *F.absolute(th), storage="f32", entropic=True)
+    t0 = ctx.totals()[0]
+    m = ctx.moments()
+    ke0 = float(np.sum((m[1] ** 2 + m[2] ** 2 + m[3] ** 2) / (2 * m[0])))
+    ctx.step(2000)
+    assert ctx.status() == 0
+    t1 = ctx.totals()[0]
+    m = ctx.moments()
+    ctx.free()
+    ke1 = float(np.sum((m[1] ** 2 + m[2] ** 2 + m[3] ** 2) / (2 * m[0])))
+    say("entropic: 2000 steps, mass %.2e energy %.2e relative, momentum %.2e, KE %.4g -> %.4g"
+        % (t1[0] / t0[0] - 1, t1[4] / t0[4] - 1, np.max(np.abs(t1[1:4])), ke0, ke1))
+    assert np.all(np.isfinite(m))
+    assert abs(t1[0] / t0[0] - 1) < 1e-5 and abs(t1[4] / t0[4] - 1) < 1e-5
+    assert np.max(np.abs(t1[1:4])) < 1e-5 * t0[0] * 0.3
+    assert ke1 < ke0
