@@ -676,6 +676,75 @@ int orc_run_model(int nx, int ny, int nz, double omega, int model, double *f, do
     return bad ? -1 : 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Kinetic walls (Sec. VII.A: diffuse walls at fixed velocity and           */
+/* temperature; reading of the multi-speed rule below)                      */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Walls normal to y, a quarter cell outside the node layers: with the layer
+ * index L = 2y + s (layer L at height L/2), the lower wall lies at -1/4 and
+ * the upper one at ny - 1/4. Populations are pushed as in orc_run_model,
+ * periodically in x and z. A post-collision population whose destination
+ * layer L + 2 c_y lies beyond a wall is taken up by that wall, and the wall
+ * gives the same mass back to the node it came from: the populations that
+ * would arrive at that node from beyond the wall (the reverses of the ones
+ * taken up) are set to sigma f_w,q, where f_w is the equilibrium of the
+ * wall's velocity and temperature at unit density (the model's equilibrium)
+ * and sigma = (mass taken up) / (sum of f_w,q over those populations): a
+ * diffuse, mass-conserving reflection.
+ * wall[8] = (ux, uy, uz, theta) of the lower wall, then of the upper wall.
+ */
+int orc_run_walls(int nx, int ny, int nz, double omega, int model, const double *wall, double *f, double *tmp,
+                  int nsteps)
+{
+    lattice_build();
+    const int64_t N = 2LL * nx * ny * nz;
+    double fw[2][NQ];
+    int rev[NQ];
+    for (int w = 0; w < 2; ++w) {
+        const double *p = wall + 4 * w;
+        int rc = (model & 3) == 1 ? orc_equilibrium_iso(1.0, p[0], p[1], p[2], fw[w], NULL, NULL, NULL)
+                                  : orc_equilibrium(1.0, p[0], p[1], p[2], p[3], fw[w], NULL, NULL, NULL);
+        if (rc != 0 || (model & 3) == 2) return -2;
+    }
+    for (int q = 0; q < NQ; ++q)
+        for (int r = 0; r < NQ; ++r)
+            if (g_c[r][0] == -g_c[q][0] && g_c[r][1] == -g_c[q][1] && g_c[r][2] == -g_c[q][2]) rev[q] = r;
+    const int64_t top = 2LL * ny - 1; /* last layer */
+    int bad = 0;
+    for (int t = 0; t < nsteps; ++t) {
+#pragma omp parallel for schedule(static) reduction(| : bad)
+        for (int64_t n = 0; n < N; ++n) {
+            double a[NQ], b[NQ];
+            const int64_t x = n % nx, y = (n / nx) % ny, z = (n / ((int64_t)nx * ny)) % nz,
+                          s = n / ((int64_t)nx * ny * nz);
+            const int64_t L = 2 * y + s;
+            for (int q = 0; q < NQ; ++q) a[q] = f[q * N + n];
+            if (orc_collide_node_model(a, omega, model, b) != 0) bad = 1;
+            double taken[2] = {0.0, 0.0}, norm[2] = {0.0, 0.0};
+            int side[NQ];
+            for (int q = 0; q < NQ; ++q) {
+                const int64_t Ld = L + (int64_t)lround(2.0 * g_c[q][1]);
+                side[q] = Ld < 0 ? 0 : Ld > top ? 1 : -1;
+                if (side[q] < 0) {
+                    tmp[q * N + push_dest(q, s, x, y, z, nx, ny, nz)] = b[q];
+                } else {
+                    taken[side[q]] += b[q];
+                    norm[side[q]] += fw[side[q]][rev[q]];
+                }
+            }
+            for (int q = 0; q < NQ; ++q)
+                if (side[q] >= 0) {
+                    const int w = side[q];
+                    tmp[rev[q] * N + n] = taken[w] / norm[w] * fw[w][rev[q]];
+                }
+        }
+        memcpy(f, tmp, sizeof(double) * (size_t)(NQ * N));
+    }
+    return bad ? -1 : 0;
+}
+
 int orc_run(int nx, int ny, int nz, double omega, double *f, double *tmp, int nsteps)
 {
     return orc_run_model(nx, ny, nz, omega, 0, f, tmp, nsteps);

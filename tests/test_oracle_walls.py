@@ -1,0 +1,81 @@
+"""Pins for the oracle's kinetic walls (Sec. VII.A: Couette flow between a
+stationary wall at T0 and a wall moving at U0 held at T1, with the
+steady temperature profile (T - T0)/dT = eta + (Ec/2) eta (1 - eta),
+Ec = U0^2/(c_p dT), c_p = 5/2). Reading of the wall rule: diffuse,
+mass-conserving reflection per node towards the wall's equilibrium, walls a
+quarter cell outside the node layers."""
+import numpy as np
+import pytest
+
+
+def _couette(orc, ny, tau, Ec, steps, U=0.02):
+    c, w, th = orc.lattice()
+    nx = nz = 1
+    N = 2 * ny
+    dT = U * U / (2.5 * Ec)
+    T0, T1 = th - dT / 2, th + dT / 2
+    L = np.array([2 * y + s for s in range(2) for y in range(ny)])
+    eta = (L / 2 + 0.25) / ny
+    f = orc.init(nx, ny, nz, np.ones(N), U * eta, np.zeros(N), np.zeros(N), T0 + dT * eta)
+    g = orc.run_walls(nx, ny, nz, 1 / tau, f, steps, ((0, 0, 0, T0), (U, 0, 0, T1)))
+    m = orc.moment_fields(g)
+    u = m[1:4] / m[0]
+    theta = (2 * m[4] / m[0] - (u * u).sum(0)) / 3
+    return f, g, eta, u, (theta - T0) / dT
+
+
+def test_rest_is_a_fixed_point_and_mass_is_kept(orc):
+    """Both walls at rest at theta0 around a uniform rest state: nothing
+    moves. Walls at different temperatures and velocities: total mass is
+    kept to rounding (the reflection returns what it takes)."""
+    c, w, th = orc.lattice()
+    nx, ny, nz = 3, 5, 2
+    N = 2 * nx * ny * nz
+    f = orc.init(nx, ny, nz, np.full(N, 1.02), np.zeros(N), np.zeros(N), np.zeros(N), np.full(N, th))
+    g = orc.run_walls(nx, ny, nz, 1 / 0.7, f, 30, ((0, 0, 0, th), (0, 0, 0, th)))
+    assert np.max(np.abs(g - f)) < 1e-14
+    rng = np.random.default_rng(5)
+    f = orc.init(nx, ny, nz, 1 + 0.01 * rng.uniform(-1, 1, N), 0.05 * rng.uniform(-1, 1, N),
+                 0.05 * rng.uniform(-1, 1, N), 0.05 * rng.uniform(-1, 1, N), th * (1 + 0.01 * rng.uniform(-1, 1, N)))
+    g = orc.run_walls(nx, ny, nz, 1 / 0.6, f, 40, ((0.03, 0, -0.01, th * 0.98), (-0.02, 0, 0.04, th * 1.03)))
+    assert abs(g.sum() / f.sum() - 1) < 1e-13
+    assert np.all(g > 0)
+
+
+def test_walls_are_periodic_copies_when_far_away(orc):
+    """Nodes more than two cells from both walls see nothing of them in one
+    step: one step with walls equals one periodic step there."""
+    c, w, th = orc.lattice()
+    nx, ny, nz = 2, 9, 2
+    N = 2 * nx * ny * nz
+    rng = np.random.default_rng(6)
+    f = orc.init(nx, ny, nz, 1 + 0.01 * rng.uniform(-1, 1, N), 0.05 * rng.uniform(-1, 1, N),
+                 0.05 * rng.uniform(-1, 1, N), 0.05 * rng.uniform(-1, 1, N), np.full(N, th))
+    g = orc.run_walls(nx, ny, nz, 1 / 0.6, f, 1, ((0.1, 0, 0, th), (0, 0, 0, 1.1 * th)))
+    h = orc.run(nx, ny, nz, 1 / 0.6, f, 1)
+    y = (np.arange(N) // nx) % ny
+    far = (y >= 2) & (y <= ny - 3)
+    assert np.max(np.abs(g[:, far] - h[:, far])) < 1e-15
+    assert np.max(np.abs(g[:, ~far] - h[:, ~far])) > 1e-6
+
+
+def test_couette_velocity_and_eckert_temperature_profiles(orc):
+    """Steady Couette flow with viscous heating (Ec = 2, U0 = 0.02, tau 0.6)
+    at H = 16 and 32 cells against the analytic profiles: velocity linear to
+    0.5% of U0, temperature within 6% and 3% of dT, the error halving with H
+    (first order in the cell size, as expected of a diffuse wall), and the
+    viscous-heating bump Ec/8 present at the centre."""
+    errs = []
+    for ny, steps in ((16, 20000), (32, 60000)):
+        f, g, eta, u, tn = _couette(orc, ny, 0.6, 2.0, steps)
+        an = eta + eta * (1 - eta)
+        errs.append(np.max(np.abs(tn - an)))
+        assert np.max(np.abs(u[0] / 0.02 - eta)) < 0.005 * 16 / ny
+        # no mean flow across or out of plane (a wall-normal velocity of
+        # 2e-5 U0 remains at the first layers: the Knudsen layer)
+        assert np.max(np.abs(u[1])) < 1e-4 * 0.02 and np.max(np.abs(u[2])) < 1e-12
+        mid = np.argmin(np.abs(eta - 0.5))
+        assert abs((tn[mid] - eta[mid]) / 0.25 - 1) < 0.2 * 16 / ny
+        assert abs(g.sum() / f.sum() - 1) < 1e-12
+    assert errs[0] < 0.06 and errs[1] < 0.03
+    assert errs[0] / errs[1] > 1.8
