@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--n", type=int, default=512, help="cells per edge of the periodic box")
     ap.add_argument("--forms", default="f16s+sr,f32,f16s,f32+sr,f32s,bf16s+sr,f16s+sr+e1,f32+e1,f16s+sr+elbm,f32+elbm",
                     help="storage forms ('+sr': stochastic rounding, '+e1': series equilibrium E1 instead of "
-                         "the entropic E2, '+elbm': entropic path length); the first is the headline")
+                         "the entropic E2, '+elbm': entropic path length, '+walls': kinetic walls normal to y); "
+                         "the first is the headline")
     ap.add_argument("--tau", type=float, default=0.6)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -94,21 +95,22 @@ def copy_reference(torch, gib, reps=5):
 
 
 def parse_form(form):
-    """'storage[+sr][+e1][+elbm]': storage form, stochastic rounding, series
-    equilibrium E1 instead of the entropic E2, entropic path length."""
+    """'storage[+sr][+e1][+elbm][+walls]': storage form, stochastic rounding,
+    series equilibrium E1 instead of the entropic E2, entropic path length,
+    kinetic walls normal to y (at rest at theta0)."""
     storage, *flags = form.split("+")
-    unknown = set(flags) - {"sr", "e1", "elbm"}
+    unknown = set(flags) - {"sr", "e1", "elbm", "walls"}
     if unknown:
         raise SystemExit("unknown form flag(s) %s in %r" % (sorted(unknown), form))
-    return storage, "sr" in flags, "e1" in flags, "elbm" in flags
+    return storage, "sr" in flags, "e1" in flags, "elbm" in flags, "walls" in flags
 
 
 def time_form(lbm, torch, F, th, n, tau, form, steps, warmup, autotune):
-    storage, sr, e1, elbm = parse_form(form)
+    storage, sr, e1, elbm, walls = parse_form(form)
     stream = torch.cuda.Stream()
     t0 = time.time()
     ctx = lbm.init([(n, n, n, tau)], *F.absolute(th), storage=storage, stream=stream, stochastic=sr, series=e1,
-                   entropic=elbm)
+                   entropic=elbm, walls=walls)
     init_s = time.time() - t0
     tune = None
     if autotune:
@@ -156,13 +158,13 @@ def time_batch(lbm, torch, form, steps, warmup, autotune):
     over every (box, tile), eager and replayed from captured graphs."""
     from paper_1909_08406_amd import workloads as wl
 
-    storage, sr, e1, elbm = parse_form(form)
+    storage, sr, e1, elbm, walls = parse_form(form)
     specs = wl.batch_specs()
     cat = wl.concat([wl.batch_fields(b) for b in specs])
     _, _, th = lbm.lattice()
     stream = torch.cuda.Stream()
     ctx = lbm.init([(b.nx, b.ny, b.nz, b.tau) for b in specs], cat[0], cat[1], cat[2], cat[3], cat[4] * th,
-                   storage=storage, stream=stream, stochastic=sr, series=e1, entropic=elbm)
+                   storage=storage, stream=stream, stochastic=sr, series=e1, entropic=elbm, walls=walls)
     del cat
     if autotune:
         ctx.autotune(reps=3)

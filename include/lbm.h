@@ -89,6 +89,23 @@ typedef enum {
                                            conserved, momentum up to O(u eta^k) terms.
                                            Not with LBM_FLAG_ISOTHERMAL. Default launch
                                            shape, as for the isothermal model. */
+#define LBM_FLAG_WALLS 16u              /* kinetic walls normal to y in every box (Sec. VII.A:
+                                           walls of given velocity and temperature; the
+                                           rule on this lattice is a reading): node layers
+                                           L = 2y + s sit at height L/2 and the walls a
+                                           quarter cell outside the first and last layer.
+                                           A population that would come from beyond a wall
+                                           is replaced: the wall returns to each node the
+                                           mass that node sent through it in the previous
+                                           step, re-emitted in the shape of the wall's
+                                           equilibrium at unit density (diffuse, mass
+                                           conserving). x and z stay periodic. Needs
+                                           ny >= 2; with the energy-conserving or the
+                                           isothermal equilibrium, not with
+                                           LBM_FLAG_SERIES_EQUILIBRIUM or LBM_FLAG_ENTROPIC
+                                           (LBM_E_UNSUPPORTED). Walls start at rest at
+                                           theta0; lbm_set_walls changes them. Default
+                                           launch shape. */
 #define LBM_FLAG_ENTROPIC 8u            /* entropic path length (Sec. IX.A: relaxation
                                            f + alpha beta (f_eq - f), beta = omega/2,
                                            alpha = 2 for BGK; Sec. IX.D: alpha from
@@ -309,6 +326,20 @@ void lbm_free(lbm_ctx *ctx);
 
 /* Static description of an error code. */
 const char *lbm_strerror(int code);
+
+/*
+ * Velocity and temperature of the two kinetic walls of one box of a context
+ * made with LBM_FLAG_WALLS (Sec. VII.A: a stationary wall and a moving wall
+ * held at different temperatures). wall[8] = (ux, uy, uz, theta) of the
+ * lower wall (below layer 0), then of the upper wall; theta absolute (not
+ * used by the isothermal model, whose walls are at theta0). A wall-normal
+ * velocity is accepted and enters only through the wall's equilibrium. The
+ * wall equilibria are computed in FP64 on the host and copied to the
+ * context's workspace, ordered after the steps already enqueued; the call
+ * synchronises the context stream. Errors: LBM_E_ARG (no walls, bad box),
+ * LBM_E_DOMAIN (non-finite values, theta <= 0), LBM_E_HIP.
+ */
+int lbm_set_walls(lbm_ctx *ctx, int32_t box, const double *wall);
 
 /*
  * Host-only self test of the library's integer helpers (division by

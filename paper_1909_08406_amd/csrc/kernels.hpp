@@ -59,6 +59,7 @@ constexpr int MODEL_E2 = 0;
 constexpr int MODEL_ISO = 1;
 constexpr int MODEL_SERIES = 2;
 constexpr int MODEL_ENTROPIC = 4;
+constexpr int MODEL_WALLS = 8;
 constexpr int MODEL_BASE_MASK = 3;
 
 // ---------------------------------------------------------------------------
@@ -498,6 +499,67 @@ __device__ __forceinline__ void collide_encode(typename ST::R x[Q], typename ST:
     });
 }
 
+// ---------------------------------------------------------------------------
+// Kinetic walls normal to y (Sec. VII.A: diffuse walls of given velocity and
+// temperature). Node layers L = 2y + s sit at height L/2; the walls lie a
+// quarter cell outside the first and the last layer. A population that would
+// arrive from beyond a wall (source layer L - 2 c_y outside) is replaced:
+// each wall returns to the node the mass the node sent through it in the
+// previous step (its own post-collision populations -c_q, which no node
+// pulls), re-emitted in the shape of the wall's equilibrium at unit density:
+//   f_q = sigma f_w,q,  sigma = sum f*_{-q} / sum f_w,q  over the replaced q.
+// In deviation form (dev = f - w rho_r; f_w,q = w_q (1 + Dw_q)) with
+// dsigma = sigma - rho_r = sum (dev_{-q} - rho_r w_q Dw_q) / sum f_w,q, the
+// new value is dev_q = w_q (dsigma + sigma Dw_q). Velocities with c_y > 0
+// can only come through the lower wall, c_y < 0 through the upper one.
+// ---------------------------------------------------------------------------
+template <class ST>
+__device__ __forceinline__ void wall_pull(typename ST::R x[Q], const char* __restrict__ src, uint64_t qbytes,
+                                          uint32_t n, int L, int top, const StepParams& p)
+{
+    using R = typename ST::R;
+    using T = typename ST::T;
+    const R rr = ST::shifted ? R(p.rho_ref) : R(1);
+    const uint64_t nbytes = uint64_t(n) * sizeof(T);
+    // deviation of a stored value of shell sh, and back
+    auto dev_of = [&](R v, int sh, double w) { return ST::shifted ? v * R(p.inv_scale[sh]) : v - R(w); };
+    auto stored_of = [&](R d, int sh, double w) { return ST::shifted ? d * R(p.scale[sh]) : d + R(w); };
+    R num[2] = {R(0), R(0)}, den[2] = {R(0), R(0)};
+    static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int vy = VEL[q].y;
+        if constexpr (vy != 0) {
+            constexpr int w = vy > 0 ? 0 : 1;
+            constexpr int r = reverse_of(q);
+            const bool beyond = vy > 0 ? L < vy : L > top + vy;
+            if (beyond) {
+                const R dw = R(p.wall_dev[w * Q + q]);
+                const R out = ST::decode(*reinterpret_cast<const T*>(src + r * qbytes + nbytes));
+                num[w] += dev_of(out, VEL[r].shell, weight(r)) - rr * R(weight(q)) * dw;
+                den[w] += R(weight(q)) * (R(1) + dw);
+            }
+        }
+    });
+    R ds[2], sg[2];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        ds[w] = den[w] > R(0) ? num[w] / den[w] : R(0);
+        sg[w] = rr + ds[w];
+    }
+    static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int vy = VEL[q].y;
+        if constexpr (vy != 0) {
+            constexpr int w = vy > 0 ? 0 : 1;
+            const bool beyond = vy > 0 ? L < vy : L > top + vy;
+            if (beyond) {
+                const R dw = R(p.wall_dev[w * Q + q]);
+                x[q] = stored_of(R(weight(q)) * fma(sg[w], dw, ds[w]), VEL[q].shell, weight(q));
+            }
+        }
+    });
+}
+
 // The step of node n of one box: src and dst are the box's first q-block
 // in the current and the other population buffer.
 template <class ST, int NEWTON, int FL, bool SR, int MODEL>
@@ -513,7 +575,7 @@ __device__ __forceinline__ void step_node(const char* __restrict__ src, char* __
 
     R x[Q];
     T out[Q];
-    if constexpr (sizeof(T) == 2 && !SR && !(MODEL & MODEL_ENTROPIC)) {
+    if constexpr (sizeof(T) == 2 && !SR && !(MODEL & (MODEL_ENTROPIC | MODEL_WALLS))) {
         // 16-bit storage, round to nearest: the raw values are also kept two
         // per 32-bit register and decoded again for the relaxation (fewer
         // live registers through the equilibrium solve). Measured faster for
@@ -544,6 +606,12 @@ __device__ __forceinline__ void step_node(const char* __restrict__ src, char* __
             x[q] = ST::decode(ld_hint(reinterpret_cast<const T*>(src + q * qbytes + uint64_t(pull_src<q>(nb))),
                                       FL & FL_NT_LOAD));
         });
+        if constexpr ((MODEL & MODEL_WALLS) != 0) {
+            // the pulls above wrapped periodically (in bounds); the ones
+            // from beyond a wall are replaced
+            const int L = int(2 * c.y + c.s), top = int(2 * p.g.ny) - 1;
+            if (L < 4 || L > top - 4) wall_pull<ST>(x, src, qbytes, n, L, top, p);
+        }
         collide_encode<ST, NEWTON, SR, MODEL>(x, out, p, p.node0 + n);
     }
     const uint32_t nbytes = n * uint32_t(sizeof(T));
@@ -611,8 +679,8 @@ constexpr int INIT_NEWTON = 6;
 // Deviations D_q (f_eq,q = w_q rho_ref (1 + D_q)) of the equilibrium of
 // (rho, u, theta) in FP64, relative to the reference state w_q rho_ref.
 // model: MODEL_E2, MODEL_ISO (theta unused) or MODEL_SERIES.
-__device__ inline void equilibrium_dev_f64(double rho, double ux, double uy, double uz, double theta,
-                                           double rho_ref, int model, double D[Q])
+__host__ __device__ inline void equilibrium_dev_f64(double rho, double ux, double uy, double uz, double theta,
+                                                    double rho_ref, int model, double D[Q])
 {
     NodeDev<double> st;
     st.rho_ref = rho_ref;

@@ -49,6 +49,14 @@ constexpr double SHELL_C2[6] = {0.0, 1.0, 4.0, 2.0, 3.0, 0.75};
 
 constexpr double weight(int q) { return SHELL_W[VEL[q].shell]; }
 
+// Index of the velocity -c_q.
+constexpr int reverse_of(int q)
+{
+    for (int r = 0; r < Q; ++r)
+        if (VEL[r].x == -VEL[q].x && VEL[r].y == -VEL[q].y && VEL[r].z == -VEL[q].z) return r;
+    return -1;
+}
+
 // theta0 = sum_i w_i c_ix^2 (Sec. III: the second weight constraint defines
 // the reference temperature; the paper leaves it as an unknown of the system).
 constexpr double theta0_value()

@@ -46,6 +46,7 @@ struct BoxDev {
     uint64_t offset;  // element offset of this box in a population buffer
     uint64_t nodes;
     uint64_t node0;   // index of the box's first node in the context
+    double* wall_dev = nullptr;  // device: the box's 2 x 41 wall deviations (kinetic walls)
 };
 
 // Block sizes of the step-kernel variants; the batched launch keeps one
@@ -59,6 +60,7 @@ struct Layout {
     uint64_t buf_bytes = 0;  // bytes per population buffer (aligned)
     uint64_t flag_off = 0, partial_off = 0, staging_off = 0, staging_bytes = 0, total = 0;
     uint64_t table_off = 0;          // BatchBox per box
+    uint64_t wall_off = 0;           // 2 x 41 doubles per box (kinetic walls)
     uint64_t tiles_off[NBLK] = {};   // (box, tile) pairs per block size
     uint64_t ntiles[NBLK] = {};
     uint64_t max_nodes = 0;
@@ -73,7 +75,8 @@ uint32_t model_of(uint32_t flags)
 {
     const uint32_t base = (flags & LBM_FLAG_ISOTHERMAL) ? uint32_t(MODEL_ISO)
                           : (flags & LBM_FLAG_SERIES_EQUILIBRIUM) ? uint32_t(MODEL_SERIES) : uint32_t(MODEL_E2);
-    return base | ((flags & LBM_FLAG_ENTROPIC) ? uint32_t(MODEL_ENTROPIC) : 0u);
+    return base | ((flags & LBM_FLAG_ENTROPIC) ? uint32_t(MODEL_ENTROPIC) : 0u) |
+           ((flags & LBM_FLAG_WALLS) ? uint32_t(MODEL_WALLS) : 0u);
 }
 
 int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
@@ -84,8 +87,11 @@ int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
     if (opts->tau_conv != LBM_TAU_LB && opts->tau_conv != LBM_TAU_PAPER) return LBM_E_ARG;
     if (opts->newton_iters < 0 || opts->newton_iters > 4) return LBM_E_ARG;
     if (opts->flags & ~uint32_t(LBM_FLAG_STOCHASTIC_ROUNDING | LBM_FLAG_ISOTHERMAL | LBM_FLAG_SERIES_EQUILIBRIUM |
-                                LBM_FLAG_ENTROPIC))
+                                LBM_FLAG_ENTROPIC | LBM_FLAG_WALLS))
         return LBM_E_ARG;
+    if ((opts->flags & LBM_FLAG_WALLS) &&
+        (opts->flags & (LBM_FLAG_SERIES_EQUILIBRIUM | LBM_FLAG_ENTROPIC)))
+        return LBM_E_UNSUPPORTED;
     if ((opts->flags & LBM_FLAG_ISOTHERMAL) && (opts->flags & LBM_FLAG_SERIES_EQUILIBRIUM)) return LBM_E_ARG;
     if ((opts->flags & LBM_FLAG_ENTROPIC) && (opts->flags & LBM_FLAG_SERIES_EQUILIBRIUM)) return LBM_E_ARG;
     if ((opts->flags & LBM_FLAG_STOCHASTIC_ROUNDING) &&
@@ -101,6 +107,7 @@ int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
         // node ids and in-q-block byte offsets are 32-bit
         if (nodes >= (1ull << 32) || nodes * uint64_t(eb) > 0xffffffffull) return LBM_E_ARG;
         if (!std::isfinite(x.tau)) return LBM_E_ARG;
+        if ((opts->flags & LBM_FLAG_WALLS) && x.ny < 2) return LBM_E_ARG;
         if (opts->tau_conv == LBM_TAU_LB && !(x.tau > 0.5)) return LBM_E_ARG;
         if (opts->tau_conv == LBM_TAU_PAPER && !(x.tau > 0.0)) return LBM_E_ARG;
         tiles += (nodes + 127) / 128;
@@ -122,7 +129,8 @@ Layout plan(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
     L.buf_bytes = align_up(L.elems * eb);
     L.flag_off = 2 * L.buf_bytes;
     L.table_off = L.flag_off + ALIGN;
-    uint64_t off = L.table_off + align_up(uint64_t(nboxes) * sizeof(BatchBox));
+    L.wall_off = L.table_off + align_up(uint64_t(nboxes) * sizeof(BatchBox));
+    uint64_t off = L.wall_off + align_up(uint64_t(nboxes) * 2 * Q * sizeof(double));
     for (int i = 0; i < NBLK; ++i) {
         for (int b = 0; b < nboxes; ++b) {
             const uint64_t nodes = 2ull * uint64_t(boxes[b].nx) * boxes[b].ny * boxes[b].nz;
@@ -182,6 +190,7 @@ struct lbm_ctx {
         p.g = b.g;
         p.omega = b.omega;
         p.node0 = uint32_t(b.node0);
+        p.wall_dev = b.wall_dev;
         p.step = steps_done;
         // the kernel's reference weights are the FP32-rounded ones
         for (int s = 0; s < 6; ++s)
@@ -304,6 +313,12 @@ int enqueue_step(lbm_ctx* ctx, int from, uint32_t step, const uint32_t* step_bas
                             break;
                         case MODEL_ISO | MODEL_ENTROPIC:
                             launch(sr, integral_constant<int, MODEL_ISO | MODEL_ENTROPIC>{}, blk, fl);
+                            break;
+                        case MODEL_E2 | MODEL_WALLS:
+                            launch(sr, integral_constant<int, MODEL_E2 | MODEL_WALLS>{}, blk, fl);
+                            break;
+                        case MODEL_ISO | MODEL_WALLS:
+                            launch(sr, integral_constant<int, MODEL_ISO | MODEL_WALLS>{}, blk, fl);
                             break;
                         default: return LBM_E_ARG;
                     }
@@ -562,6 +577,8 @@ static int init_impl(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const 
     ctx->flag = reinterpret_cast<uint32_t*>(ctx->mem + ctx->L.flag_off);
     ctx->step_ctr = reinterpret_cast<uint32_t*>(ctx->mem + ctx->L.flag_off + COUNTER_OFF);
     ctx->table = reinterpret_cast<BatchBox*>(ctx->mem + ctx->L.table_off);
+    for (size_t b = 0; b < ctx->boxes.size(); ++b)
+        ctx->boxes[b].wall_dev = reinterpret_cast<double*>(ctx->mem + ctx->L.wall_off) + b * 2 * Q;
     for (int i = 0; i < NBLK; ++i) ctx->tiles[i] = reinterpret_cast<uint2*>(ctx->mem + ctx->L.tiles_off[i]);
     ctx->schedule = nboxes > 1 ? LBM_SCHEDULE_BATCHED : LBM_SCHEDULE_PER_BOX;
     ctx->partials = reinterpret_cast<double*>(ctx->mem + ctx->L.partial_off);
@@ -581,6 +598,10 @@ static int init_impl(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const 
     set_shift(ctx);
 
     if (hipMemsetAsync(ctx->flag, 0, ALIGN, ctx->stream) != hipSuccess) return fail(LBM_E_HIP);
+    // kinetic walls start at rest at theta0: their equilibrium is w_q
+    if (hipMemsetAsync(ctx->mem + ctx->L.wall_off, 0, ctx->boxes.size() * 2 * Q * sizeof(double), ctx->stream) !=
+        hipSuccess)
+        return fail(LBM_E_HIP);
     const double* fields[5] = {rho, ux, uy, uz, theta};
 
     if (shifted && ctx->storage != LBM_F32_SHIFT) {
@@ -881,7 +902,8 @@ int lbm_get_info(lbm_ctx* ctx, lbm_info* info)
     info->flags = (ctx->stochastic ? LBM_FLAG_STOCHASTIC_ROUNDING : 0u) |
                   (base == MODEL_ISO ? LBM_FLAG_ISOTHERMAL : 0u) |
                   (base == MODEL_SERIES ? LBM_FLAG_SERIES_EQUILIBRIUM : 0u) |
-                  ((ctx->base.model & MODEL_ENTROPIC) ? LBM_FLAG_ENTROPIC : 0u);
+                  ((ctx->base.model & MODEL_ENTROPIC) ? LBM_FLAG_ENTROPIC : 0u) |
+                  ((ctx->base.model & MODEL_WALLS) ? LBM_FLAG_WALLS : 0u);
     info->steps_done = ctx->steps_done;
     info->nboxes = int32_t(ctx->boxes.size());
     info->nodes = int64_t(ctx->L.elems / Q);
@@ -1007,6 +1029,27 @@ const char* lbm_strerror(int code)
         case LBM_E_UNSUPPORTED: return "unsupported request";
         default: return "unknown error";
     }
+}
+
+int lbm_set_walls(lbm_ctx* ctx, int32_t box, const double* wall)
+{
+    if (!ctx || !wall || box < 0 || box >= int32_t(ctx->boxes.size())) return LBM_E_ARG;
+    if (!(ctx->base.model & MODEL_WALLS)) return LBM_E_ARG;
+    const int model = int(ctx->base.model & MODEL_BASE_MASK);
+    double dev[2 * Q];
+    for (int w = 0; w < 2; ++w) {
+        const double* u = wall + 4 * w;
+        for (int k = 0; k < 4; ++k)
+            if (!std::isfinite(u[k])) return LBM_E_DOMAIN;
+        if (model != MODEL_ISO && !(u[3] > 0.0)) return LBM_E_DOMAIN;
+        // the wall's equilibrium at unit density, as deviations f_w,q / w_q - 1
+        equilibrium_dev_f64(1.0, u[0], u[1], u[2], model == MODEL_ISO ? THETA0 : u[3], 1.0, model, dev + w * Q);
+        for (int q = 0; q < Q; ++q)
+            if (!(dev[w * Q + q] > -1.0) || !std::isfinite(dev[w * Q + q])) return LBM_E_DOMAIN;
+    }
+    HIPCHK(hipMemcpyAsync(ctx->boxes[box].wall_dev, dev, sizeof(dev), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return LBM_OK;
 }
 
 int lbm_collide_host(int32_t precision, int32_t newton, uint32_t flags, double omega, const double* f_in,

@@ -19,6 +19,7 @@ FLAG_STOCHASTIC_ROUNDING = 1
 FLAG_ISOTHERMAL = 2
 FLAG_SERIES_EQUILIBRIUM = 4
 FLAG_ENTROPIC = 8
+FLAG_WALLS = 16
 TAU_LB, TAU_PAPER = 0, 1
 SHIFT_AUTO = -1000
 STORAGE = {"f64": F64, "f32": F32, "f16s": F16_SHIFT, "bf16s": BF16_SHIFT, "f32s": F32_SHIFT}
@@ -86,6 +87,7 @@ SIGNATURES = {
     "lbm_debug_pull_map": (ctypes.c_int, [_vp, ctypes.c_int32, _lp]),
     "lbm_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
     "lbm_set_step_counter": (ctypes.c_int, [_vp, ctypes.c_uint32]),
+    "lbm_set_walls": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
     "lbm_num_variants": (ctypes.c_int, []),
     "lbm_variant_desc": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_uint32)]),
@@ -145,18 +147,19 @@ def _boxes(boxes):
 
 
 def _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic=False, seed=0, isothermal=False, series=False,
-          entropic=False):
+          entropic=False, walls=False):
     st = STORAGE[storage] if isinstance(storage, str) else int(storage)
     flags = ((FLAG_STOCHASTIC_ROUNDING if stochastic else 0) | (FLAG_ISOTHERMAL if isothermal else 0)
-             | (FLAG_SERIES_EQUILIBRIUM if series else 0) | (FLAG_ENTROPIC if entropic else 0))
+             | (FLAG_SERIES_EQUILIBRIUM if series else 0) | (FLAG_ENTROPIC if entropic else 0)
+             | (FLAG_WALLS if walls else 0))
     return Opts(st, int(tau_conv), float(rho0), int(newton_iters),
                 SHIFT_AUTO if shift_exp is None else int(shift_exp), flags, int(seed) & 0xffffffff)
 
 
 def workspace_size(boxes, storage="f32", tau_conv=TAU_LB, rho0=1.0, newton_iters=0, shift_exp=None,
-                   stochastic=False, isothermal=False, series=False, entropic=False):
+                   stochastic=False, isothermal=False, series=False, entropic=False, walls=False):
     bx = _boxes(boxes)
-    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, 0, isothermal, series, entropic)
+    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, 0, isothermal, series, entropic, walls)
     out = ctypes.c_uint64(0)
     _check(lib().lbm_workspace_size(bx, len(boxes), ctypes.byref(op), ctypes.byref(out)), "lbm_workspace_size")
     return int(out.value)
@@ -214,6 +217,14 @@ class Context:
         f = np.zeros(NQ * self.nodes)
         _check(lib().lbm_get_populations(self.handle, _d(f)), "lbm_get_populations")
         return f
+
+    def set_walls(self, box, lower, upper):
+        """lbm_set_walls: (ux, uy, uz, theta) of the lower and the upper wall
+        of one box (theta absolute)."""
+        w = np.ascontiguousarray(list(lower) + list(upper), dtype=np.float64)
+        if w.size != 8:
+            raise ValueError("two (ux, uy, uz, theta) expected")
+        _check(lib().lbm_set_walls(self.handle, int(box), _d(w)), "lbm_set_walls")
 
     def set_populations(self, f):
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
@@ -298,14 +309,15 @@ class Context:
 
 def init(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0, newton_iters=0,
          shift_exp=None, stream=None, torch_workspace=True, stochastic=False, seed=0, isothermal=False,
-         series=False, entropic=False):
+         series=False, entropic=False, walls=False):
     """lbm_init. boxes: [(nx, ny, nz, tau), ...]; nodal FP64 fields of all
     boxes concatenated (theta absolute; not used by the isothermal model).
     stream: a torch.cuda.Stream (or None for the library's own). With
     torch_workspace the device memory is a torch uint8 tensor held by the
     returned Context."""
     bx = _boxes(boxes)
-    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, seed, isothermal, series, entropic)
+    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, seed, isothermal, series, entropic,
+               walls)
     arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (rho, ux, uy, uz, theta)]
     nodes = sum(2 * b[0] * b[1] * b[2] for b in boxes)
     for a in arrs:
@@ -316,7 +328,7 @@ def init(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0
     if torch_workspace:
         import torch
         ws_bytes = workspace_size(boxes, storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, isothermal,
-                                  series, entropic)
+                                  series, entropic, walls)
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
         ws_ptr = ws.data_ptr()
     sptr = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
@@ -329,13 +341,14 @@ def init(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0
 
 def init_device(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, rho0=1.0, newton_iters=0,
                 shift_exp=None, stream=None, stochastic=False, seed=0, isothermal=False, series=False,
-                entropic=False):
+                entropic=False, walls=False):
     """lbm_init_device: the five fields are contiguous float64 torch CUDA
     tensors (all boxes concatenated); the equilibrium is built from them on
     the device. The workspace is a torch uint8 tensor held by the Context."""
     import torch
     bx = _boxes(boxes)
-    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, seed, isothermal, series, entropic)
+    op = _opts(storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, seed, isothermal, series, entropic,
+               walls)
     nodes = sum(2 * b[0] * b[1] * b[2] for b in boxes)
     fields = (rho, ux, uy, uz, theta)
     for a in fields:
@@ -344,7 +357,7 @@ def init_device(boxes, rho, ux, uy, uz, theta, storage="f32", tau_conv=TAU_LB, r
         if a.numel() != nodes:
             raise ValueError("field has %d values, boxes have %d nodes" % (a.numel(), nodes))
     ws_bytes = workspace_size(boxes, storage, tau_conv, rho0, newton_iters, shift_exp, stochastic, isothermal, series,
-                              entropic)
+                              entropic, walls)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     sptr = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
     if stream is not None:

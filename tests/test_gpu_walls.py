@@ -1,0 +1,188 @@
+"""Kinetic walls on the GPU (LBM_FLAG_WALLS; Sec. VII.A: diffuse walls of
+given velocity and temperature, the Couette flow with viscous heating and its
+Eckert temperature profile). Parity against the oracle's wall run, launch-path
+identity, mass conservation, and the steady Couette profiles."""
+import numpy as np
+import pytest
+
+from paper_1909_08406_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    from paper_1909_08406_amd import lbm
+    return lbm
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def test_walls_at_rest_keep_a_rest_state(L):
+    """Both walls at rest at theta0 around a uniform rest state: a fixed
+    point (the wall equilibrium is the lattice weights)."""
+    dims = (6, 5, 4)
+    n = 2 * dims[0] * dims[1] * dims[2]
+    _, _, th = L.lattice()
+    for storage, tol in (("f64", 1e-15), ("f32", 2e-7)):
+        ctx = L.init([(*dims, 0.7)], np.full(n, 1.02), np.zeros(n), np.zeros(n), np.zeros(n), np.full(n, th),
+                     storage=storage, walls=True)
+        assert ctx.info()["flags"] & L.FLAG_WALLS
+        f0 = ctx.get_populations()
+        ctx.step(20)
+        f1 = ctx.get_populations()
+        assert ctx.status() == 0
+        ctx.free()
+        assert np.max(np.abs(f1 - f0)) <= tol
+
+
+WALLS = ((0.03, 0.0, -0.01, 0.98), (-0.02, 0.0, 0.04, 1.03))  # (u, theta / theta0) lower, upper
+
+
+@pytest.mark.parametrize("storage,model,tol", [("f64", "thermal", 1e-12), ("f64", "isothermal", 1e-12),
+                                               ("f32", "thermal", 1e-5), ("f32", "isothermal", 1e-5)])
+def test_walls_vs_oracle(L, orc, storage, model, tol):
+    """Ragged 7x6x5 box between moving walls at different temperatures,
+    random state, 12 steps, against the oracle's wall run. The GPU holds the
+    collision of the oracle's state (an equilibrium start is a fixed point of
+    the collision), so moments compare directly and populations against the
+    oracle's collision of its state; normwise 1e-12 (FP64) and 1e-5 (FP32),
+    populations within 10x."""
+    dims, tau, steps = (7, 6, 5), 0.6, 12
+    iso = model == "isothermal"
+    F = wl.random_state(*dims, seed=51, amp_u=0.05, amp_rho=0.01, amp_theta=0.01)
+    _, _, th = L.lattice()
+    walls = tuple((u[0], u[1], u[2], u[3] * th) for u in WALLS)
+    ctx = L.init([(*dims, tau)], *F.absolute(th), storage=storage, isothermal=iso, walls=True)
+    ctx.set_walls(0, *walls)
+    ctx.step(steps)
+    m = ctx.moments()
+    g = ctx.get_populations().reshape(41, -1)
+    assert ctx.status() == 0
+    ctx.free()
+    f = orc.run_walls(*dims, 1 / tau, orc.init(*dims, *F.absolute(th), model=model), steps, walls, model=model)
+    gref = orc.collide_field(*dims, 1 / tau, f, model=model)
+    m_ref = orc.moment_fields(f)
+    k = 4 if iso else 5
+    err = float(np.max(np.abs(m[:k] - m_ref[:k])) / np.max(np.abs(m_ref[:k])))
+    perr = float(np.max(np.abs(g - gref)) / np.max(np.abs(gref)))
+    # the walls did something: the periodic run differs near them
+    fp = orc.run(*dims, 1 / tau, orc.init(*dims, *F.absolute(th), model=model), steps, model=model)
+    diff = float(np.max(np.abs(orc.moment_fields(fp)[:k] - m_ref[:k])) / np.max(np.abs(m_ref[:k])))
+    say("walls %s %s: moment error %.2e, population error %.2e (periodic differs by %.2e)"
+        % (storage, model, err, perr, diff))
+    assert err <= tol and perr <= 10 * tol
+    assert diff > 1e3 * err
+
+
+def test_walls_batched_and_graph_match_per_box(L):
+    """Three boxes with different walls, FP16-shifted with stochastic
+    rounding: batched schedule and graph replays bit-identical to per-box
+    launches; mass kept by the walls (FP64 totals, to the storage's
+    rounding)."""
+    boxes = [(12, 8, 6, 0.52), (9, 7, 5, 0.7), (16, 6, 4, 0.6)]
+    _, _, th = L.lattice()
+    fields = [wl.random_state(b[0], b[1], b[2], seed=60 + i, amp_u=0.02, amp_rho=0.005, amp_theta=0.005)
+              for i, b in enumerate(boxes)]
+    args = wl.concat(fields)
+    out = {}
+    for name, tune in (("per_box", dict(schedule="per_box", graph_steps=0)),
+                       ("batched", dict(schedule="batched", graph_steps=0)),
+                       ("graph", dict(schedule="batched", graph_steps=4))):
+        ctx = L.init(boxes, args[0], args[1], args[2], args[3], args[4] * th, storage="f16s", stochastic=True,
+                     walls=True)
+        for b in range(3):
+            ctx.set_walls(b, (0.01 * b, 0, 0, th * (1 - 0.01 * b)), (-0.02, 0, 0.01 * b, th * (1 + 0.02 * b)))
+        ctx.set_tuning(**tune)
+        t0 = ctx.totals()
+        ctx.step(10)
+        t1 = ctx.totals()
+        out[name] = ctx.get_populations()
+        assert ctx.status() == 0
+        ctx.free()
+        assert np.max(np.abs(t1[:, 0] / t0[:, 0] - 1)) < 1e-6
+    assert np.array_equal(out["per_box"], out["batched"])
+    assert np.array_equal(out["per_box"], out["graph"])
+
+
+def _couette_profile(ctx, ny, nx, nz, U, T0, dT):
+    m = ctx.moments()
+    u = m[1:4] / m[0]
+    theta = (2 * m[4] / m[0] - (u * u).sum(0)) / 3
+    # average over x and z per layer L = 2y + s
+    n = np.arange(m.shape[1])
+    y = (n // nx) % ny
+    s = n // (nx * ny * nz)
+    Lyr = 2 * y + s
+    tl = np.array([theta[Lyr == k].mean() for k in range(2 * ny)])
+    ul = np.array([u[0][Lyr == k].mean() for k in range(2 * ny)])
+    return (tl - T0) / dT, ul / U
+
+
+@pytest.mark.parametrize("storage,tol_an", [("f64", 0.03), ("f32", 0.035)])
+def test_couette_viscous_heating_eckert_profile(L, orc, storage, tol_an):
+    """Couette flow between a stationary wall at T0 and a wall moving at
+    U0 = 0.02 held at T1 (Ec = 2: dT = U0^2/(c_p Ec), c_p = 5/2), 32 cells
+    high, tau 0.6, run to steady state (60,000 steps). The GPU profile
+    against the oracle's steady state (1e-9 of dT in FP64) and against the
+    analytic (T - T0)/dT = eta + (Ec/2) eta (1 - eta): within 3% of dT, the
+    first-order wall error the oracle shows at this height."""
+    nx, ny, nz, tau, U, Ec, steps = 4, 32, 4, 0.6, 0.02, 2.0, 60000
+    _, _, th = L.lattice()
+    dT = U * U / (2.5 * Ec)
+    T0, T1 = th - dT / 2, th + dT / 2
+    n = 2 * nx * ny * nz
+    idx = np.arange(n)
+    Lyr = 2 * ((idx // nx) % ny) + idx // (nx * ny * nz)
+    eta = (Lyr / 2 + 0.25) / ny
+    ctx = L.init([(nx, ny, nz, tau)], np.ones(n), U * eta, np.zeros(n), np.zeros(n), T0 + dT * eta,
+                 storage=storage, walls=True)
+    ctx.set_walls(0, (0, 0, 0, T0), (U, 0, 0, T1))
+    ctx.step(steps)
+    assert ctx.status() == 0
+    tn, un = _couette_profile(ctx, ny, nx, nz, U, T0, dT)
+    ctx.free()
+    el = (np.arange(2 * ny) / 2 + 0.25) / ny
+    an = el + Ec / 2 * el * (1 - el)
+    err_an = float(np.max(np.abs(tn - an)))
+    # the oracle's steady state on a 1x32x1 column (x and z play no part)
+    e1 = (np.array([2 * y + s for s in range(2) for y in range(ny)]) / 2 + 0.25) / ny
+    f = orc.init(1, ny, 1, np.ones(2 * ny), U * e1, np.zeros(2 * ny), np.zeros(2 * ny), T0 + dT * e1)
+    f = orc.run_walls(1, ny, 1, 1 / tau, f, steps, ((0, 0, 0, T0), (U, 0, 0, T1)))
+    mo = orc.moment_fields(f)
+    uo = mo[1:4] / mo[0]
+    to = (2 * mo[4] / mo[0] - (uo * uo).sum(0)) / 3
+    Lo = np.array([2 * y + s for s in range(2) for y in range(ny)])
+    ref = np.array([(to[Lo == k][0] - T0) / dT for k in range(2 * ny)])
+    err_or = float(np.max(np.abs(tn - ref)))
+    say("Couette %s: temperature vs analytic %.4f of dT, vs oracle %.2e of dT; velocity vs linear %.4f of U0"
+        % (storage, err_an, err_or, np.max(np.abs(un - el))))
+    assert err_an < tol_an
+    assert err_or < (1e-9 if storage == "f64" else 2e-2)
+    assert np.max(np.abs(un - el)) < 0.003
+
+
+def test_walls_rejected_combinations(L):
+    _, _, th = L.lattice()
+    n = 2 * 4 * 4 * 4
+    fields = (np.ones(n), np.zeros(n), np.zeros(n), np.zeros(n), np.full(n, th))
+    with pytest.raises(Exception):
+        L.init([(4, 4, 4, 0.6)], *fields, storage="f32", walls=True, entropic=True)
+    with pytest.raises(Exception):
+        L.init([(4, 1, 4, 0.6)], np.ones(32), np.zeros(32), np.zeros(32), np.zeros(32), np.full(32, th),
+               storage="f32", walls=True)
+    ctx = L.init([(4, 4, 4, 0.6)], *fields, storage="f32")
+    with pytest.raises(Exception):
+        ctx.set_walls(0, (0, 0, 0, th), (0, 0, 0, th))
+    ctx.free()
+    ctx = L.init([(4, 4, 4, 0.6)], *fields, storage="f32", walls=True)
+    with pytest.raises(Exception):
+        ctx.set_walls(0, (0, 0, 0, -1.0), (0, 0, 0, th))
+    with pytest.raises(Exception):
+        ctx.set_walls(1, (0, 0, 0, th), (0, 0, 0, th))
+    ctx.free()
