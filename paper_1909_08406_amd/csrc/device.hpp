@@ -673,6 +673,18 @@ struct StoreF16S {
     __device__ static R decode(T v) { return float(v); }
     __device__ static T encode(R v) { return _Float16(v); }  // round to nearest even
     __device__ static T encode_sr(R v, uint32_t r) { return _Float16(sr_truncate(v, r, 13)); }
+    // Two values with the two 16-bit halves of r: the random bits are added
+    // below the kept mantissa and the pair is converted with round toward
+    // zero in one instruction (the same rounding as encode_sr in the normal
+    // FP16 range).
+    __device__ static void encode_sr2(R a, R b, uint32_t r, T& oa, T& ob)
+    {
+        const float ra = __uint_as_float(__float_as_uint(a) + (r & 0x1fffu));
+        const float rb = __uint_as_float(__float_as_uint(b) + ((r >> 16) & 0x1fffu));
+        const auto h = __builtin_amdgcn_cvt_pkrtz(ra, rb);
+        oa = h[0];
+        ob = h[1];
+    }
     __device__ static R load(const T* p) { return float(*p); }
     __device__ static void store(T* p, R v) { *p = _Float16(v); }
 };
@@ -705,6 +717,14 @@ struct StoreBF16S {
     __device__ static R decode(T v) { return float(v); }
     __device__ static T encode(R v) { return __bf16(v); }
     __device__ static T encode_sr(R v, uint32_t r) { return __bf16(sr_truncate(v, r, 16)); }
+    // Two values with the two 16-bit halves of r: the random bits are added
+    // below the kept mantissa and the upper halves are the result.
+    __device__ static void encode_sr2(R a, R b, uint32_t r, T& oa, T& ob)
+    {
+        const uint32_t ua = __float_as_uint(a) + (r & 0xffffu), ub = __float_as_uint(b) + (r >> 16);
+        oa = __builtin_bit_cast(T, uint16_t(ua >> 16));
+        ob = __builtin_bit_cast(T, uint16_t(ub >> 16));
+    }
     __device__ static R load(const T* p) { return float(*p); }
     __device__ static void store(T* p, R v) { *p = __bf16(v); }
 };

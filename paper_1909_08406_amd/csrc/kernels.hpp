@@ -489,8 +489,17 @@ __device__ __forceinline__ void collide_encode(typename ST::R x[Q], typename ST:
         if constexpr (SR) {
             if constexpr (q % 2 == 0) rw = xorshift32(rs);
             const uint32_t rb = (q % 2 == 0) ? (rw & 0xffffu) : (rw >> 16);
-            if constexpr (ST::shifted) out[q] = ST::encode_sr(y[q], rb);
-            else out[q] = sr_add(x[q], y[q], rb);  // stochastic rounding exists for FP32 only
+            // 16-bit storage: populations in pairs sharing one random word
+            // (measured 2-3% faster, except with the series equilibrium,
+            // where it measured 1.7% slower and the single encoder stays)
+            if constexpr (ST::shifted && sizeof(typename ST::T) == 2 && (MODEL & MODEL_BASE_MASK) != MODEL_SERIES) {
+                if constexpr (q % 2 == 0 && q + 1 < Q) ST::encode_sr2(y[q], y[q + 1], rw, out[q], out[q + 1]);
+                else if constexpr (q % 2 == 0) out[q] = ST::encode_sr(y[q], rb);
+            } else if constexpr (ST::shifted) {
+                out[q] = ST::encode_sr(y[q], rb);
+            } else {
+                out[q] = sr_add(x[q], y[q], rb);  // stochastic rounding exists for FP32 only
+            }
         } else {
             if constexpr (ST::shifted) out[q] = ST::encode(y[q]);
             else if constexpr (DEV_IN_PLACE<R>) out[q] = ST::encode((x[q] + R(weight(q))) + y[q]);  // f = d + w
