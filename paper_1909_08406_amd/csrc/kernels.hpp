@@ -406,11 +406,30 @@ __host__ __device__ __forceinline__ void collide(R x[Q], R y[Q], const CollideCo
 #pragma unroll
         for (int s = 0; s < 6; ++s) omw[s] = cc.omw[s] * ah;
     }
-    static_for<Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        if constexpr (KEEP_D) relax(qc, y[q]);
-        else relax(qc, dmul(gibbs_dev<q, R>(S), kap));
-    });
+    if constexpr (KEEP_D) {
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            relax(qc, y[q]);
+        });
+    } else {
+        // omw_s D_q = omw_s (e_q + kappa + e_q kappa) = A_s e_q + B_s with
+        // e_q the Gibbs factor's deviation: one FMA per population
+        R A[6], B[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            A[s] = omw[s] * (R(1) + kap);
+            B[s] = omw[s] * kap;
+        }
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int sh = VEL[q].shell;
+            const R e = gibbs_dev<q, R>(S);
+            if constexpr (SHIFTED && !std::is_same<XR, NoReload>::value) y[q] = fma(om1, xr(qc), fma(A[sh], e, B[sh]));
+            else if constexpr (SHIFTED) y[q] = fma(om1, x[q], fma(A[sh], e, B[sh]));
+            else if constexpr (DEV_IN_PLACE<R>) y[q] = fma(A[sh], e, fma(-om, x[q], B[sh]));
+            else y[q] = fma(A[sh], e, fma(-om, x[q] - R(weight(q)), B[sh]));
+        });
+    }
 }
 
 // ---------------------------------------------------------------------------
