@@ -451,7 +451,8 @@ static double path_dh(const double *f, const double *x, double p1, double a)
  * (the equilibrium), so the root lies in (1, a_max), where a_max =
  * min_{x_i < 0} (-1/x_i) keeps the mirror state positive. The search is
  * limited to (1, a_cap], a_cap = (1 - 2^-10) a_max; if dH(a_cap) <= 0 the
- * path length is a_cap. f = f_eq gives alpha = 2. Plain bisection.
+ * path length is a_cap. f = f_eq gives alpha = 2 (also when rounding leaves
+ * no x_i < 0, which in exact arithmetic means f = f_eq). Plain bisection.
  */
 double orc_path_length(const double *f, const double *feq)
 {
@@ -463,8 +464,11 @@ double orc_path_length(const double *f, const double *feq)
         if (x[i] != 0.0) any = 1;
         if (x[i] < xmin) xmin = x[i];
     }
-    if (!any) return 2.0;
-    const double acap = (xmin < 0.0 ? -1.0 / xmin : INFINITY) * (1.0 - 1.0 / 1024.0);
+    /* f = f_eq: alpha = 2. Without a negative x_i, sum_i f_i x_i = 0 forces
+     * every x_i to zero in exact arithmetic, so that case is f = f_eq up to
+     * rounding, and takes the same value. */
+    if (!any || !(xmin < 0.0)) return 2.0;
+    const double acap = (-1.0 / xmin) * (1.0 - 1.0 / 1024.0);
     double lo = 1.0, hi = acap;
     if (!(path_dh(f, x, p1, hi) > 0.0)) return hi;
     for (int it = 0; it < 400; ++it) {

@@ -119,6 +119,24 @@ def test_equilibrium_is_a_fixed_point_and_alpha_two(orc):
     assert orc.path_length(feq, feq) == 2.0
     out = orc.collide_node(feq, 1.5, entropic=True)
     assert np.max(np.abs(out - feq)) <= 1e-15
+    # rounding that leaves no x_i < 0 (f = f_eq in exact arithmetic)
+    f = feq * (1 + 1e-16 * np.arange(41) / 41)
+    assert orc.path_length(f, feq) == 2.0
+
+
+def test_entropic_run_from_equilibrium_fields(orc):
+    """A run started from equilibrium populations (where f and the
+    recomputed f_eq agree to rounding at every node) stays finite and keeps
+    mass and energy."""
+    from paper_1909_08406_amd import workloads as wl
+    dims = (7, 6, 5)
+    F = wl.random_state(*dims, seed=51, amp_u=0.05, amp_rho=0.01, amp_theta=0.01)
+    _, _, th = orc.lattice()
+    f0 = orc.init(*dims, *F.absolute(th))
+    f = orc.run(*dims, 1 / 0.6, f0, 5, entropic=True)
+    assert np.all(np.isfinite(f))
+    t0, t1 = orc.totals(f0), orc.totals(f)
+    assert abs(t1[0] / t0[0] - 1) < 1e-14 and abs(t1[4] / t0[4] - 1) < 1e-14
 
 
 @pytest.mark.parametrize("model", ["thermal", "isothermal"])
