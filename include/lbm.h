@@ -101,8 +101,9 @@ typedef enum {
                                            equilibrium at unit density (diffuse, mass
                                            conserving). x and z stay periodic. Needs
                                            ny >= 2; with the energy-conserving or the
-                                           isothermal equilibrium, not with
-                                           LBM_FLAG_SERIES_EQUILIBRIUM or LBM_FLAG_ENTROPIC
+                                           isothermal equilibrium and optionally
+                                           LBM_FLAG_ENTROPIC, not with
+                                           LBM_FLAG_SERIES_EQUILIBRIUM
                                            (LBM_E_UNSUPPORTED). Walls start at rest at
                                            theta0; lbm_set_walls changes them. Default
                                            launch shape. */

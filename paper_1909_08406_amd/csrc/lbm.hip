@@ -89,9 +89,7 @@ int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
     if (opts->flags & ~uint32_t(LBM_FLAG_STOCHASTIC_ROUNDING | LBM_FLAG_ISOTHERMAL | LBM_FLAG_SERIES_EQUILIBRIUM |
                                 LBM_FLAG_ENTROPIC | LBM_FLAG_WALLS))
         return LBM_E_ARG;
-    if ((opts->flags & LBM_FLAG_WALLS) &&
-        (opts->flags & (LBM_FLAG_SERIES_EQUILIBRIUM | LBM_FLAG_ENTROPIC)))
-        return LBM_E_UNSUPPORTED;
+    if ((opts->flags & LBM_FLAG_WALLS) && (opts->flags & LBM_FLAG_SERIES_EQUILIBRIUM)) return LBM_E_UNSUPPORTED;
     if ((opts->flags & LBM_FLAG_ISOTHERMAL) && (opts->flags & LBM_FLAG_SERIES_EQUILIBRIUM)) return LBM_E_ARG;
     if ((opts->flags & LBM_FLAG_ENTROPIC) && (opts->flags & LBM_FLAG_SERIES_EQUILIBRIUM)) return LBM_E_ARG;
     if ((opts->flags & LBM_FLAG_STOCHASTIC_ROUNDING) &&
@@ -319,6 +317,12 @@ int enqueue_step(lbm_ctx* ctx, int from, uint32_t step, const uint32_t* step_bas
                             break;
                         case MODEL_ISO | MODEL_WALLS:
                             launch(sr, integral_constant<int, MODEL_ISO | MODEL_WALLS>{}, blk, fl);
+                            break;
+                        case MODEL_E2 | MODEL_ENTROPIC | MODEL_WALLS:
+                            launch(sr, integral_constant<int, MODEL_E2 | MODEL_ENTROPIC | MODEL_WALLS>{}, blk, fl);
+                            break;
+                        case MODEL_ISO | MODEL_ENTROPIC | MODEL_WALLS:
+                            launch(sr, integral_constant<int, MODEL_ISO | MODEL_ENTROPIC | MODEL_WALLS>{}, blk, fl);
                             break;
                         default: return LBM_E_ARG;
                     }

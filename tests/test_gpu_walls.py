@@ -44,29 +44,33 @@ def test_walls_at_rest_keep_a_rest_state(L):
 WALLS = ((0.03, 0.0, -0.01, 0.98), (-0.02, 0.0, 0.04, 1.03))  # (u, theta / theta0) lower, upper
 
 
-@pytest.mark.parametrize("storage,model,tol", [("f64", "thermal", 1e-12), ("f64", "isothermal", 1e-12),
-                                               ("f32", "thermal", 1e-5), ("f32", "isothermal", 1e-5)])
-def test_walls_vs_oracle(L, orc, storage, model, tol):
+@pytest.mark.parametrize("storage,model,entropic,tol", [
+    ("f64", "thermal", False, 1e-12), ("f64", "isothermal", False, 1e-12), ("f32", "thermal", False, 1e-5),
+    ("f32", "isothermal", False, 1e-5), ("f64", "thermal", True, 1e-12), ("f32", "thermal", True, 1e-5),
+    ("f64", "isothermal", True, 1e-12)])
+def test_walls_vs_oracle(L, orc, storage, model, entropic, tol):
     """Ragged 7x6x5 box between moving walls at different temperatures,
     random state, 12 steps, against the oracle's wall run. The GPU holds the
     collision of the oracle's state (an equilibrium start is a fixed point of
     the collision), so moments compare directly and populations against the
     oracle's collision of its state; normwise 1e-12 (FP64) and 1e-5 (FP32),
-    populations within 10x."""
+    populations within 10x. Also with the entropic path length, whose
+    collision then ends each step on both sides."""
     dims, tau, steps = (7, 6, 5), 0.6, 12
     iso = model == "isothermal"
     F = wl.random_state(*dims, seed=51, amp_u=0.05, amp_rho=0.01, amp_theta=0.01)
     _, _, th = L.lattice()
     walls = tuple((u[0], u[1], u[2], u[3] * th) for u in WALLS)
-    ctx = L.init([(*dims, tau)], *F.absolute(th), storage=storage, isothermal=iso, walls=True)
+    ctx = L.init([(*dims, tau)], *F.absolute(th), storage=storage, isothermal=iso, walls=True, entropic=entropic)
     ctx.set_walls(0, *walls)
     ctx.step(steps)
     m = ctx.moments()
     g = ctx.get_populations().reshape(41, -1)
     assert ctx.status() == 0
     ctx.free()
-    f = orc.run_walls(*dims, 1 / tau, orc.init(*dims, *F.absolute(th), model=model), steps, walls, model=model)
-    gref = orc.collide_field(*dims, 1 / tau, f, model=model)
+    f = orc.run_walls(*dims, 1 / tau, orc.init(*dims, *F.absolute(th), model=model), steps, walls, model=model,
+                      entropic=entropic)
+    gref = orc.collide_field(*dims, 1 / tau, f, model=model, entropic=entropic)
     m_ref = orc.moment_fields(f)
     k = 4 if iso else 5
     err = float(np.max(np.abs(m[:k] - m_ref[:k])) / np.max(np.abs(m_ref[:k])))
@@ -74,8 +78,8 @@ def test_walls_vs_oracle(L, orc, storage, model, tol):
     # the walls did something: the periodic run differs near them
     fp = orc.run(*dims, 1 / tau, orc.init(*dims, *F.absolute(th), model=model), steps, model=model)
     diff = float(np.max(np.abs(orc.moment_fields(fp)[:k] - m_ref[:k])) / np.max(np.abs(m_ref[:k])))
-    say("walls %s %s: moment error %.2e, population error %.2e (periodic differs by %.2e)"
-        % (storage, model, err, perr, diff))
+    say("walls %s %s%s: moment error %.2e, population error %.2e (periodic differs by %.2e)"
+        % (storage, model, " entropic" if entropic else "", err, perr, diff))
     assert err <= tol and perr <= 10 * tol
     assert diff > 1e3 * err
 
@@ -172,7 +176,7 @@ def test_walls_rejected_combinations(L):
     n = 2 * 4 * 4 * 4
     fields = (np.ones(n), np.zeros(n), np.zeros(n), np.zeros(n), np.full(n, th))
     with pytest.raises(Exception):
-        L.init([(4, 4, 4, 0.6)], *fields, storage="f32", walls=True, entropic=True)
+        L.init([(4, 4, 4, 0.6)], *fields, storage="f32", walls=True, series=True)
     with pytest.raises(Exception):
         L.init([(4, 1, 4, 0.6)], np.ones(32), np.zeros(32), np.zeros(32), np.zeros(32), np.full(32, th),
                storage="f32", walls=True)
@@ -186,3 +190,24 @@ def test_walls_rejected_combinations(L):
     with pytest.raises(Exception):
         ctx.set_walls(1, (0, 0, 0, th), (0, 0, 0, th))
     ctx.free()
+
+
+@pytest.mark.parametrize("dims", [(5, 2, 3), (4, 3, 2)])
+def test_walls_thin_boxes_vs_oracle(L, orc, dims):
+    """Boxes 2 and 3 cells high, where nodes take populations from both walls
+    in one step: FP64 against the oracle's wall run (1e-12 normwise)."""
+    tau, steps = 0.6, 12
+    F = wl.random_state(*dims, seed=71, amp_u=0.05, amp_rho=0.01, amp_theta=0.01)
+    _, _, th = L.lattice()
+    walls = tuple((u[0], u[1], u[2], u[3] * th) for u in WALLS)
+    ctx = L.init([(*dims, tau)], *F.absolute(th), storage="f64", walls=True)
+    ctx.set_walls(0, *walls)
+    ctx.step(steps)
+    m = ctx.moments()
+    assert ctx.status() == 0
+    ctx.free()
+    f = orc.run_walls(*dims, 1 / tau, orc.init(*dims, *F.absolute(th)), steps, walls)
+    m_ref = orc.moment_fields(f)
+    err = float(np.max(np.abs(m - m_ref)) / np.max(np.abs(m_ref)))
+    say("thin box %s: moment error %.2e" % (dims, err))
+    assert err <= 1e-12
