@@ -55,6 +55,7 @@ struct Geom {
     uint32_t nxy;    // nx*ny
     uint32_t plane;  // nx*ny*nz, nodes of one sublattice
     uint32_t N;      // 2*plane
+    uint32_t qs;     // elements from one q-block of the box to the next (>= N)
     FastDiv dx, dy, dz;
 };
 
@@ -65,6 +66,7 @@ inline Geom make_geom(uint32_t nx, uint32_t ny, uint32_t nz)
     g.nxy = nx * ny;
     g.plane = nx * ny * nz;
     g.N = 2 * g.plane;
+    g.qs = g.N;
     g.dx = make_fastdiv(nx);
     g.dy = make_fastdiv(ny);
     g.dz = make_fastdiv(nz);

@@ -599,7 +599,7 @@ __device__ __forceinline__ void step_node(const char* __restrict__ src, char* __
     const Coord c = decode(n, p.g);
     Nbr nb;
     make_nbr(p.g, c, nb, uint32_t(sizeof(T)));
-    const uint64_t qbytes = uint64_t(p.g.N) * sizeof(T);
+    const uint64_t qbytes = uint64_t(p.g.qs) * sizeof(T);
 
     R x[Q];
     T out[Q];
@@ -779,7 +779,7 @@ struct InitFields {
 };
 
 template <class ST>
-__global__ __launch_bounds__(BLOCK) void k_init(typename ST::T* __restrict__ f, uint32_t N, uint32_t n0,
+__global__ __launch_bounds__(BLOCK) void k_init(typename ST::T* __restrict__ f, uint32_t qs, uint32_t n0,
                                                 uint32_t count, InitFields fields, StepParams p, int mode,
                                                 float* maxdev)
 {
@@ -807,7 +807,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(typename ST::T* __restrict__ f, 
                 double v;
                 if constexpr (ST::shifted) v = d * double(p.scale[sh]);
                 else v = SHELL_W[sh] + d;
-                ST::store(f + size_t(q) * N + n0 + i, typename ST::R(v));
+                ST::store(f + size_t(q) * qs + n0 + i, typename ST::R(v));
             }
         });
         if (bad || !in_domain) atomicOr(p.flag, 1u);
@@ -819,23 +819,23 @@ __global__ __launch_bounds__(BLOCK) void k_init(typename ST::T* __restrict__ f, 
 // FP64 decoding helpers for the diagnostics kernels.
 // ---------------------------------------------------------------------------
 template <class ST, int q>
-__device__ inline double dev64(const typename ST::T* f, size_t N, uint32_t n, const StepParams& p)
+__device__ inline double dev64(const typename ST::T* f, size_t qs, uint32_t n, const StepParams& p)
 {
-    double v = double(ST::load(f + size_t(q) * N + n));
+    double v = double(ST::load(f + size_t(q) * qs + n));
     if constexpr (ST::shifted) v *= double(p.inv_scale[VEL[q].shell]);
     return v;
 }
 
 // rho, jx, jy, jz, E of node n in FP64.
 template <class ST>
-__device__ inline void node_moments64(const typename ST::T* f, size_t N, uint32_t n, const StepParams& p,
+__device__ inline void node_moments64(const typename ST::T* f, size_t qs, uint32_t n, const StepParams& p,
                                       double m[5])
 {
     double rd = 0, jx = 0, jy = 0, jz = 0, e4 = 0;
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         constexpr HalfVel v = VEL[q];
-        const double d = dev64<ST, q>(f, N, n, p);
+        const double d = dev64<ST, q>(f, qs, n, p);
         rd += d;
         jx += double(v.x) * d;
         jy += double(v.y) * d;
@@ -850,13 +850,13 @@ __device__ inline void node_moments64(const typename ST::T* f, size_t N, uint32_
 }
 
 template <class ST>
-__global__ __launch_bounds__(BLOCK) void k_moments(const typename ST::T* __restrict__ f, uint32_t N, uint32_t n0,
+__global__ __launch_bounds__(BLOCK) void k_moments(const typename ST::T* __restrict__ f, uint32_t qs, uint32_t n0,
                                                    uint32_t count, StepParams p, double* __restrict__ out)
 {
     const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= count) return;
     double m[5];
-    node_moments64<ST>(f, N, n0 + i, p, m);
+    node_moments64<ST>(f, qs, n0 + i, p, m);
 #pragma unroll
     for (int k = 0; k < 5; ++k) out[size_t(k) * count + i] = m[k];
 }
@@ -895,7 +895,7 @@ __global__ __launch_bounds__(BLOCK) void k_totals(const typename ST::T* __restri
     double acc[5] = {0, 0, 0, 0, 0};
     for (uint32_t n = blockIdx.x * BLOCK + threadIdx.x; n < N; n += gridDim.x * BLOCK) {
         double m[5];
-        node_moments64<ST>(f, N, n, p, m);
+        node_moments64<ST>(f, p.g.qs, n, p, m);
 #pragma unroll
         for (int k = 0; k < 5; ++k) acc[k] += m[k];
     }
@@ -933,7 +933,7 @@ __global__ __launch_bounds__(BLOCK) void k_project(const typename ST::T* __restr
     for (int k = 0; k < 2 * PROJ_FIELDS; ++k) acc[k] = 0.0;
     for (uint32_t n = blockIdx.x * BLOCK + threadIdx.x; n < N; n += gridDim.x * BLOCK) {
         double m[5];
-        node_moments64<ST>(f, N, n, p, m);
+        node_moments64<ST>(f, p.g.qs, n, p, m);
         const Coord c = decode(n, p.g);
         const double h = 0.5 * double(c.s);
         const double ph = kx * (double(c.x) + h) + ky * (double(c.y) + h) + kz * (double(c.z) + h);
@@ -988,7 +988,7 @@ __global__ __launch_bounds__(BLOCK) void k_gather(const typename ST::T* __restri
     const int64_t k = idx[i];
     const uint32_t q = uint32_t(k / N), n = uint32_t(k - int64_t(q) * N);
     const int sh = q == 0 ? 0 : q < 7 ? 1 : q < 13 ? 2 : q < 25 ? 3 : q < 33 ? 4 : 5;
-    double v = double(ST::load(f + size_t(q) * N + n));
+    double v = double(ST::load(f + size_t(q) * p.g.qs + n));
     if constexpr (ST::shifted) v *= double(p.inv_scale[sh]);
     out[i] = SHELL_W[sh] * p.rho_ref + v;
 }

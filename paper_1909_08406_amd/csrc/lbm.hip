@@ -79,6 +79,21 @@ uint32_t model_of(uint32_t flags)
            ((flags & LBM_FLAG_WALLS) ? uint32_t(MODEL_WALLS) : 0u);
 }
 
+// Elements from one q-block of a box to the next: the block rounded up to
+// 256 bytes, plus 1 MiB + 256 bytes for 16-bit storage when the block is a
+// multiple of 1 MiB. Without it the 41 streams of a step sit at the same
+// address modulo a large power of two (a 512^3 FP16 q-block is 2^29 bytes);
+// measured on MI355X at 512^3: FP16-shifted+SR 9.25 -> 8.69 ms per step,
+// BF16-shifted+SR 9.65 -> 9.09 ms, while FP32 and FP64 gained nothing (FP64
+// lost 2%), so they keep the plain stride.
+constexpr uint64_t QPAD_16 = (1u << 20) + 256;
+uint32_t qstride(uint64_t nodes, int eb)
+{
+    const uint64_t bytes = align_up(nodes * uint64_t(eb));
+    const uint64_t pad = (eb == 2 && bytes % (1u << 20) == 0) ? QPAD_16 : 0;
+    return uint32_t((bytes + pad) / uint64_t(eb));
+}
+
 int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
 {
     if (!boxes || !opts || nboxes < 1) return LBM_E_ARG;
@@ -103,7 +118,7 @@ int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
         if (x.nx < 1 || x.ny < 1 || x.nz < 1 || x.reserved != 0) return LBM_E_ARG;
         const uint64_t nodes = 2ull * uint64_t(x.nx) * uint64_t(x.ny) * uint64_t(x.nz);
         // node ids and in-q-block byte offsets are 32-bit
-        if (nodes >= (1ull << 32) || nodes * uint64_t(eb) > 0xffffffffull) return LBM_E_ARG;
+        if (nodes >= (1ull << 32) || nodes * uint64_t(eb) > 0xffffffffull - (QPAD_16 + 256)) return LBM_E_ARG;
         if (!std::isfinite(x.tau)) return LBM_E_ARG;
         if ((opts->flags & LBM_FLAG_WALLS) && x.ny < 2) return LBM_E_ARG;
         if (opts->tau_conv == LBM_TAU_LB && !(x.tau > 0.5)) return LBM_E_ARG;
@@ -121,7 +136,7 @@ Layout plan(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
     const int eb = elem_bytes(opts->storage);
     for (int b = 0; b < nboxes; ++b) {
         const uint64_t nodes = 2ull * uint64_t(boxes[b].nx) * boxes[b].ny * boxes[b].nz;
-        L.elems += uint64_t(Q) * nodes;
+        L.elems += uint64_t(Q) * qstride(nodes, eb);
         L.max_nodes = std::max(L.max_nodes, nodes);
     }
     L.buf_bytes = align_up(L.elems * eb);
@@ -443,7 +458,7 @@ int run_init(lbm_ctx* ctx, const BoxDev& b, uint64_t node_base, const double* co
             using ST = decltype(st);
             using T = typename ST::T;
             T* f = reinterpret_cast<T*>(ctx->buf(ctx->cur)) + b.offset;
-            hipLaunchKernelGGL((k_init<ST>), dim3(nblocks(cnt)), dim3(BLOCK), 0, ctx->stream, f, uint32_t(b.nodes),
+            hipLaunchKernelGGL((k_init<ST>), dim3(nblocks(cnt)), dim3(BLOCK), 0, ctx->stream, f, b.g.qs,
                                uint32_t(n0), uint32_t(cnt), in, p, mode, maxdev);
             return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
         });
@@ -546,9 +561,10 @@ static int init_impl(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const 
         BoxDev d;
         d.g = make_geom(uint32_t(boxes[b].nx), uint32_t(boxes[b].ny), uint32_t(boxes[b].nz));
         d.nodes = d.g.N;
+        d.g.qs = qstride(d.nodes, elem_bytes(opts->storage));
         d.offset = off;
         d.node0 = node0;
-        off += uint64_t(Q) * d.nodes;
+        off += uint64_t(Q) * d.g.qs;
         node0 += d.nodes;
         d.omega = opts->tau_conv == LBM_TAU_LB ? 1.0 / boxes[b].tau : 2.0 / (2.0 * boxes[b].tau + 1.0);
         ctx->boxes.push_back(d);
@@ -556,7 +572,7 @@ static int init_impl(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const 
 
     // domain check of host fields before any device work (device fields are
     // checked by the init kernel, which raises the flag read below)
-    const uint64_t total = device_fields ? 0 : ctx->L.elems / Q;
+    const uint64_t total = device_fields ? 0 : node0;
     for (uint64_t i = 0; i < total; ++i) {
         if (!(rho[i] > 0.0) || !(theta[i] > 0.0) || !std::isfinite(rho[i]) || !std::isfinite(theta[i]) ||
             !std::isfinite(ux[i]) || !std::isfinite(uy[i]) || !std::isfinite(uz[i])) {
@@ -717,7 +733,7 @@ int lbm_moments(lbm_ctx* ctx, double* rho, double* jx, double* jy, double* jz, d
                 using T = typename ST::T;
                 const T* f = reinterpret_cast<const T*>(ctx->buf(ctx->cur)) + b.offset;
                 hipLaunchKernelGGL((k_moments<ST>), dim3(nblocks(cnt)), dim3(BLOCK), 0, ctx->stream, f,
-                                   uint32_t(b.nodes), uint32_t(n0), uint32_t(cnt), p, stage);
+                                   b.g.qs, uint32_t(n0), uint32_t(cnt), p, stage);
                 return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
             });
             if (rc) return rc;
@@ -803,7 +819,7 @@ int lbm_get_populations(lbm_ctx* ctx, double* f)
                 int rc = dispatch_storage(ctx->storage, [&](auto st) {
                     using ST = decltype(st);
                     using T = typename ST::T;
-                    const T* fq = reinterpret_cast<const T*>(ctx->buf(ctx->cur)) + b.offset + uint64_t(q) * b.nodes + n0;
+                    const T* fq = reinterpret_cast<const T*>(ctx->buf(ctx->cur)) + b.offset + uint64_t(q) * b.g.qs + n0;
                     hipLaunchKernelGGL((k_get<ST>), dim3(nblocks(cnt)), dim3(BLOCK), 0, ctx->stream, fq,
                                        uint32_t(cnt), ctx->base.inv_scale[sh], SHELL_W[sh] * ctx->base.rho_ref, stage);
                     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
@@ -835,7 +851,7 @@ int lbm_set_populations(lbm_ctx* ctx, const double* f)
                 int rc = dispatch_storage(ctx->storage, [&](auto st) {
                     using ST = decltype(st);
                     using T = typename ST::T;
-                    T* fq = reinterpret_cast<T*>(ctx->buf(ctx->cur)) + b.offset + uint64_t(q) * b.nodes + n0;
+                    T* fq = reinterpret_cast<T*>(ctx->buf(ctx->cur)) + b.offset + uint64_t(q) * b.g.qs + n0;
                     hipLaunchKernelGGL((k_set<ST>), dim3(nblocks(cnt)), dim3(BLOCK), 0, ctx->stream, fq,
                                        uint32_t(cnt), ctx->base.scale[sh], SHELL_W[sh] * ctx->base.rho_ref, stage);
                     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
@@ -921,8 +937,10 @@ int lbm_get_info(lbm_ctx* ctx, lbm_info* info)
                   ((ctx->base.model & MODEL_WALLS) ? LBM_FLAG_WALLS : 0u);
     info->steps_done = ctx->steps_done;
     info->nboxes = int32_t(ctx->boxes.size());
-    info->nodes = int64_t(ctx->L.elems / Q);
-    info->bytes_per_step = int64_t(2 * ctx->L.elems * uint64_t(elem_bytes(ctx->storage)));
+    uint64_t nodes = 0;
+    for (const BoxDev& b : ctx->boxes) nodes += b.nodes;
+    info->nodes = int64_t(nodes);
+    info->bytes_per_step = int64_t(2 * uint64_t(Q) * nodes * uint64_t(elem_bytes(ctx->storage)));
     info->block_threads = ctx->base.model != MODEL_E2 ? 256 : VARIANTS[ctx->variant].blk;
     info->variant = ctx->variant;
     info->device_bytes = ctx->L.total;
