@@ -70,6 +70,7 @@ def _load():
         "orc_collide_field_model": (i, [i, i, i, d, i, _dp, _dp]),
         "orc_run_model": (i, [i, i, i, d, i, _dp, _dp, i]),
         "orc_run_walls": (i, [i, i, i, d, i, _dp, _dp, _dp, i]),
+        "orc_run_walls_kind": (i, [i, i, i, d, i, _dp, _ip, _dp, _dp, i]),
         "orc_pull_map": (None, [i, i, i, _lp]),
         "orc_push_map": (None, [i, i, i, _lp]),
         "orc_pull_src_nodes": (None, [i, i, i, _lp, l, _lp]),
@@ -278,12 +279,13 @@ def run(nx, ny, nz, omega, f, nsteps, model="thermal", entropic=False):
     return f
 
 
-def run_walls(nx, ny, nz, omega, f, nsteps, walls, model="thermal", entropic=False):
+def run_walls(nx, ny, nz, omega, f, nsteps, walls, model="thermal", entropic=False, kinds=(0, 0)):
     """Like run, with kinetic walls normal to y a quarter cell outside the
     first and last node layers (diffuse, mass-conserving reflection towards
     each wall's equilibrium). walls = ((ux, uy, uz, theta) lower,
     (ux, uy, uz, theta) upper), theta absolute (unused by the isothermal
-    model). Periodic in x and z."""
+    model). kinds: 0 diffuse, 1 specular (mirror image in y) per wall.
+    Periodic in x and z."""
     if ny < 2:
         raise ValueError("walls need ny >= 2")
     f = _pops(f, 2 * nx * ny * nz, copy=True)
@@ -291,8 +293,9 @@ def run_walls(nx, ny, nz, omega, f, nsteps, walls, model="thermal", entropic=Fal
     w = _f64(walls).reshape(-1)
     if w.size != 8:
         raise ValueError("walls: two (ux, uy, uz, theta)")
-    rc = _load().orc_run_walls(nx, ny, nz, float(omega), _model(model, entropic), _d(w), _d(f), _d(tmp),
-                               int(nsteps))
+    k = (ctypes.c_int * 2)(int(kinds[0]), int(kinds[1]))
+    rc = _load().orc_run_walls_kind(nx, ny, nz, float(omega), _model(model, entropic), _d(w),
+                                    ctypes.cast(k, _ip), _d(f), _d(tmp), int(nsteps))
     if rc != 0:
         raise RuntimeError("oracle wall run failed (%d)" % rc)
     return f

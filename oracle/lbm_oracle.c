@@ -696,16 +696,19 @@ int orc_run_model(int nx, int ny, int nz, double omega, int model, double *f, do
  * taken up) are set to sigma f_w,q, where f_w is the equilibrium of the
  * wall's velocity and temperature at unit density (the model's equilibrium)
  * and sigma = (mass taken up) / (sum of f_w,q over those populations): a
- * diffuse, mass-conserving reflection.
- * wall[8] = (ux, uy, uz, theta) of the lower wall, then of the upper wall.
+ * diffuse, mass-conserving reflection. A specular wall (kind 1; the inviscid
+ * planar wall of Sec. VI.B) instead returns each population taken up as its
+ * mirror image (c_x, -c_y, c_z) at the same node.
+ * wall[8] = (ux, uy, uz, theta) of the lower wall, then of the upper wall;
+ * kind[2] = 0 diffuse, 1 specular, for the lower and the upper wall.
  */
-int orc_run_walls(int nx, int ny, int nz, double omega, int model, const double *wall, double *f, double *tmp,
-                  int nsteps)
+int orc_run_walls_kind(int nx, int ny, int nz, double omega, int model, const double *wall, const int *kind,
+                       double *f, double *tmp, int nsteps)
 {
     lattice_build();
     const int64_t N = 2LL * nx * ny * nz;
     double fw[2][NQ];
-    int rev[NQ];
+    int rev[NQ], mir[NQ];
     for (int w = 0; w < 2; ++w) {
         const double *p = wall + 4 * w;
         int rc = (model & 3) == 1 ? orc_equilibrium_iso(1.0, p[0], p[1], p[2], fw[w], NULL, NULL, NULL)
@@ -714,7 +717,10 @@ int orc_run_walls(int nx, int ny, int nz, double omega, int model, const double 
     }
     for (int q = 0; q < NQ; ++q)
         for (int r = 0; r < NQ; ++r)
+        {
             if (g_c[r][0] == -g_c[q][0] && g_c[r][1] == -g_c[q][1] && g_c[r][2] == -g_c[q][2]) rev[q] = r;
+            if (g_c[r][0] == g_c[q][0] && g_c[r][1] == -g_c[q][1] && g_c[r][2] == g_c[q][2]) mir[q] = r;
+        }
     const int64_t top = 2LL * ny - 1; /* last layer */
     int bad = 0;
     for (int t = 0; t < nsteps; ++t) {
@@ -741,12 +747,20 @@ int orc_run_walls(int nx, int ny, int nz, double omega, int model, const double 
             for (int q = 0; q < NQ; ++q)
                 if (side[q] >= 0) {
                     const int w = side[q];
-                    tmp[rev[q] * N + n] = taken[w] / norm[w] * fw[w][rev[q]];
+                    if (kind[w] == 1) tmp[mir[q] * N + n] = b[q];
+                    else tmp[rev[q] * N + n] = taken[w] / norm[w] * fw[w][rev[q]];
                 }
         }
         memcpy(f, tmp, sizeof(double) * (size_t)(NQ * N));
     }
     return bad ? -1 : 0;
+}
+
+int orc_run_walls(int nx, int ny, int nz, double omega, int model, const double *wall, double *f, double *tmp,
+                  int nsteps)
+{
+    const int kind[2] = {0, 0};
+    return orc_run_walls_kind(nx, ny, nz, omega, model, wall, kind, f, tmp, nsteps);
 }
 
 int orc_run(int nx, int ny, int nz, double omega, double *f, double *tmp, int nsteps)

@@ -132,6 +132,21 @@ def gaussian_pulse_2d(nx, ny, nz=1, eps=1e-3, b=8.0):
     return Fields(nx, ny, nz, rho, ux, uy, uz, th)
 
 
+def pulse_over_wall_2d(nx, ny, nz=1, eps=1e-4, b=20.0, height=100.0, u0=0.0):
+    """2D pulse above a wall normal to y: rho = 1 + eps exp(-ln2 r^2 / b^2)
+    with r the x-y distance from (nx/2, height - 1/4) (the wall lies a
+    quarter cell below the first node layer; periodic minimum image in x),
+    uniform velocity (u0, 0, 0), theta = theta0."""
+    x, y, z = positions(nx, ny, nz)
+    d = x - 0.5 * nx
+    d = d - nx * np.round(d / nx)
+    dy = y - (height - 0.25)
+    rho = 1.0 + eps * np.exp(-np.log(2.0) * (d * d + dy * dy) / (b * b))
+    _, ux, uy, uz, th = _rest(nx, ny, nz)
+    ux = np.full_like(ux, u0)
+    return Fields(nx, ny, nz, rho, ux, uy, uz, th)
+
+
 def random_state(nx, ny, nz, seed=0, amp_rho=1e-2, amp_u=5e-2, amp_theta=2e-2):
     """Independent uniform perturbations per node (parity-test input):
     rho = 1 + U(-a, a), u_a = U(-b, b), theta/theta0 = 1 + U(-c, c)."""

@@ -79,3 +79,34 @@ def test_couette_velocity_and_eckert_temperature_profiles(orc):
         assert abs(g.sum() / f.sum() - 1) < 1e-12
     assert errs[0] < 0.06 and errs[1] < 0.03
     assert errs[0] / errs[1] > 1.8
+
+
+def test_specular_walls_keep_mass_energy_and_tangential_momentum(orc):
+    """Specular walls (the inviscid planar wall of Sec. VI.B): each population
+    taken up returns as its mirror image (c_x, -c_y, c_z), so mass, energy and
+    the momentum along the walls are kept to rounding, whatever the state."""
+    from paper_1909_08406_amd import workloads as wl
+    c, w, th = orc.lattice()
+    dims = (4, 5, 3)
+    F = wl.random_state(*dims, seed=3, amp_u=0.05)
+    f = orc.init(*dims, *F.absolute(th))
+    g = orc.run_walls(*dims, 1 / 0.6, f, 20, ((0.1, 0, 0, th), (0, 0, 0, 1.2 * th)), kinds=(1, 1))
+    t0, t1 = orc.totals(f), orc.totals(g)
+    assert abs(t1[0] / t0[0] - 1) < 1e-14 and abs(t1[4] / t0[4] - 1) < 1e-14
+    assert abs(t1[1] - t0[1]) < 1e-13 and abs(t1[3] - t0[3]) < 1e-13
+    # the wall-normal momentum is not kept: the walls push back
+    assert abs(t1[2] - t0[2]) > 1e-6
+
+
+def test_specular_walls_keep_a_uniform_flow_along_them(orc):
+    """A uniform flow along specular walls is a fixed point (an inviscid wall
+    exerts no shear); along diffuse walls at rest it is not."""
+    c, w, th = orc.lattice()
+    nx, ny, nz = 3, 4, 2
+    N = 2 * nx * ny * nz
+    f = orc.init(nx, ny, nz, np.ones(N), np.full(N, 0.1), np.zeros(N), np.full(N, -0.05), np.full(N, th))
+    walls = ((0, 0, 0, th), (0, 0, 0, th))
+    g = orc.run_walls(nx, ny, nz, 1 / 0.6, f, 25, walls, kinds=(1, 1))
+    assert np.max(np.abs(g - f)) < 1e-14  # rounding of 25 equilibrium solves
+    h = orc.run_walls(nx, ny, nz, 1 / 0.6, f, 25, walls, kinds=(0, 0))
+    assert np.max(np.abs(h - f)) > 1e-4
