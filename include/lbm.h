@@ -337,10 +337,26 @@ const char *lbm_strerror(int code);
  * velocity is accepted and enters only through the wall's equilibrium. The
  * wall equilibria are computed in FP64 on the host and copied to the
  * context's workspace, ordered after the steps already enqueued; the call
- * synchronises the context stream. Errors: LBM_E_ARG (no walls, bad box),
+ * synchronises the context stream. Both walls are made diffuse
+ * (lbm_set_walls_kind below chooses). Errors: LBM_E_ARG (no walls, bad box),
  * LBM_E_DOMAIN (non-finite values, theta <= 0), LBM_E_HIP.
  */
 int lbm_set_walls(lbm_ctx *ctx, int32_t box, const double *wall);
+
+/* Kinds of kinetic wall. */
+#define LBM_WALL_DIFFUSE 0   /* re-emission in the shape of the wall's equilibrium (Sec. VII.A) */
+#define LBM_WALL_SPECULAR 1  /* each population taken up returns as its mirror image (c_x, -c_y, c_z)
+                                at the same node: the inviscid planar wall of Sec. VI.B; keeps mass,
+                                energy and the momentum along the wall; the wall's velocity and
+                                temperature play no part */
+
+/*
+ * As lbm_set_walls, with the kind of each wall: kind[2] = kind of the lower
+ * and of the upper wall (LBM_WALL_DIFFUSE or LBM_WALL_SPECULAR; wall[8] is
+ * checked in both cases). Errors as lbm_set_walls; LBM_E_ARG for an unknown
+ * kind.
+ */
+int lbm_set_walls_kind(lbm_ctx *ctx, int32_t box, const double *wall, const int32_t *kind);
 
 /*
  * Host-only self test of the library's integer helpers (division by

@@ -747,7 +747,7 @@ struct StepParams {
     uint32_t node0;        // index of the box's first node in the context (random-bit stream)
     const uint32_t* step_base;  // null, or a device counter added to step (graph replays)
     uint32_t model;        // equilibrium: 0 energy conserving (E2), 1 isothermal, 2 series (E1)
-    const double* wall_dev;  // kinetic walls: f_w,q / w_q - 1 of the lower then the upper wall (2 x 41)
+    const double* wall_dev;  // kinetic walls, lower then upper: f_w,q / w_q - 1 (41) and the kind (0 diffuse, 1 specular)
 };
 
 // Counter-based random bits for stochastic rounding: one hash per node and

@@ -540,7 +540,11 @@ __device__ __forceinline__ void collide_encode(typename ST::R x[Q], typename ST:
 // dsigma = sigma - rho_r = sum (dev_{-q} - rho_r w_q Dw_q) / sum f_w,q, the
 // new value is dev_q = w_q (dsigma + sigma Dw_q). Velocities with c_y > 0
 // can only come through the lower wall, c_y < 0 through the upper one.
+// A specular wall (the inviscid planar wall of Sec. VI.B) returns instead
+// the node's own post-collision population (c_x, -c_y, c_z): same shell, so
+// the stored value is taken as it is.
 // ---------------------------------------------------------------------------
+constexpr int WALL_STRIDE = Q + 1;  // per wall: 41 deviations, then the kind
 template <class ST>
 __device__ __forceinline__ void wall_pull(typename ST::R x[Q], const char* __restrict__ src, uint64_t qbytes,
                                           uint32_t n, int L, int top, const StepParams& p)
@@ -552,6 +556,7 @@ __device__ __forceinline__ void wall_pull(typename ST::R x[Q], const char* __res
     // deviation of a stored value of shell sh, and back
     auto dev_of = [&](R v, int sh, double w) { return ST::shifted ? v * R(p.inv_scale[sh]) : v - R(w); };
     auto stored_of = [&](R d, int sh, double w) { return ST::shifted ? d * R(p.scale[sh]) : d + R(w); };
+    const bool spec[2] = {p.wall_dev[Q] != 0.0, p.wall_dev[WALL_STRIDE + Q] != 0.0};
     R num[2] = {R(0), R(0)}, den[2] = {R(0), R(0)};
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
@@ -560,8 +565,8 @@ __device__ __forceinline__ void wall_pull(typename ST::R x[Q], const char* __res
             constexpr int w = vy > 0 ? 0 : 1;
             constexpr int r = reverse_of(q);
             const bool beyond = vy > 0 ? L < vy : L > top + vy;
-            if (beyond) {
-                const R dw = R(p.wall_dev[w * Q + q]);
+            if (beyond && !spec[w]) {
+                const R dw = R(p.wall_dev[w * WALL_STRIDE + q]);
                 const R out = ST::decode(*reinterpret_cast<const T*>(src + r * qbytes + nbytes));
                 num[w] += dev_of(out, VEL[r].shell, weight(r)) - rr * R(weight(q)) * dw;
                 den[w] += R(weight(q)) * (R(1) + dw);
@@ -581,8 +586,13 @@ __device__ __forceinline__ void wall_pull(typename ST::R x[Q], const char* __res
             constexpr int w = vy > 0 ? 0 : 1;
             const bool beyond = vy > 0 ? L < vy : L > top + vy;
             if (beyond) {
-                const R dw = R(p.wall_dev[w * Q + q]);
-                x[q] = stored_of(R(weight(q)) * fma(sg[w], dw, ds[w]), VEL[q].shell, weight(q));
+                if (spec[w]) {
+                    constexpr int m = mirror_y_of(q);
+                    x[q] = ST::decode(*reinterpret_cast<const T*>(src + m * qbytes + nbytes));
+                } else {
+                    const R dw = R(p.wall_dev[w * WALL_STRIDE + q]);
+                    x[q] = stored_of(R(weight(q)) * fma(sg[w], dw, ds[w]), VEL[q].shell, weight(q));
+                }
             }
         }
     });

@@ -49,6 +49,14 @@ constexpr double SHELL_C2[6] = {0.0, 1.0, 4.0, 2.0, 3.0, 0.75};
 
 constexpr double weight(int q) { return SHELL_W[VEL[q].shell]; }
 
+// Index of the velocity (c_x, -c_y, c_z).
+constexpr int mirror_y_of(int q)
+{
+    for (int r = 0; r < Q; ++r)
+        if (VEL[r].x == VEL[q].x && VEL[r].y == -VEL[q].y && VEL[r].z == VEL[q].z) return r;
+    return -1;
+}
+
 // Index of the velocity -c_q.
 constexpr int reverse_of(int q)
 {

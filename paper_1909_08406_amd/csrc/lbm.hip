@@ -46,7 +46,7 @@ struct BoxDev {
     uint64_t offset;  // element offset of this box in a population buffer
     uint64_t nodes;
     uint64_t node0;   // index of the box's first node in the context
-    double* wall_dev = nullptr;  // device: the box's 2 x 41 wall deviations (kinetic walls)
+    double* wall_dev = nullptr;  // device: the box's two walls, 41 deviations and the kind each
 };
 
 // Block sizes of the step-kernel variants; the batched launch keeps one
@@ -60,7 +60,7 @@ struct Layout {
     uint64_t buf_bytes = 0;  // bytes per population buffer (aligned)
     uint64_t flag_off = 0, partial_off = 0, staging_off = 0, staging_bytes = 0, total = 0;
     uint64_t table_off = 0;          // BatchBox per box
-    uint64_t wall_off = 0;           // 2 x 41 doubles per box (kinetic walls)
+    uint64_t wall_off = 0;           // 2 x (41 + 1) doubles per box (kinetic walls)
     uint64_t tiles_off[NBLK] = {};   // (box, tile) pairs per block size
     uint64_t ntiles[NBLK] = {};
     uint64_t max_nodes = 0;
@@ -143,7 +143,7 @@ Layout plan(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
     L.flag_off = 2 * L.buf_bytes;
     L.table_off = L.flag_off + ALIGN;
     L.wall_off = L.table_off + align_up(uint64_t(nboxes) * sizeof(BatchBox));
-    uint64_t off = L.wall_off + align_up(uint64_t(nboxes) * 2 * Q * sizeof(double));
+    uint64_t off = L.wall_off + align_up(uint64_t(nboxes) * 2 * WALL_STRIDE * sizeof(double));
     for (int i = 0; i < NBLK; ++i) {
         for (int b = 0; b < nboxes; ++b) {
             const uint64_t nodes = 2ull * uint64_t(boxes[b].nx) * boxes[b].ny * boxes[b].nz;
@@ -609,7 +609,7 @@ static int init_impl(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const 
     ctx->step_ctr = reinterpret_cast<uint32_t*>(ctx->mem + ctx->L.flag_off + COUNTER_OFF);
     ctx->table = reinterpret_cast<BatchBox*>(ctx->mem + ctx->L.table_off);
     for (size_t b = 0; b < ctx->boxes.size(); ++b)
-        ctx->boxes[b].wall_dev = reinterpret_cast<double*>(ctx->mem + ctx->L.wall_off) + b * 2 * Q;
+        ctx->boxes[b].wall_dev = reinterpret_cast<double*>(ctx->mem + ctx->L.wall_off) + b * 2 * WALL_STRIDE;
     for (int i = 0; i < NBLK; ++i) ctx->tiles[i] = reinterpret_cast<uint2*>(ctx->mem + ctx->L.tiles_off[i]);
     ctx->schedule = nboxes > 1 ? LBM_SCHEDULE_BATCHED : LBM_SCHEDULE_PER_BOX;
     ctx->partials = reinterpret_cast<double*>(ctx->mem + ctx->L.partial_off);
@@ -630,8 +630,8 @@ static int init_impl(lbm_ctx** out, const lbm_box* boxes, int32_t nboxes, const 
 
     if (hipMemsetAsync(ctx->flag, 0, ALIGN, ctx->stream) != hipSuccess) return fail(LBM_E_HIP);
     // kinetic walls start at rest at theta0: their equilibrium is w_q
-    if (hipMemsetAsync(ctx->mem + ctx->L.wall_off, 0, ctx->boxes.size() * 2 * Q * sizeof(double), ctx->stream) !=
-        hipSuccess)
+    if (hipMemsetAsync(ctx->mem + ctx->L.wall_off, 0, ctx->boxes.size() * 2 * WALL_STRIDE * sizeof(double),
+                       ctx->stream) != hipSuccess)
         return fail(LBM_E_HIP);
     const double* fields[5] = {rho, ux, uy, uz, theta};
 
@@ -1064,25 +1064,36 @@ const char* lbm_strerror(int code)
     }
 }
 
-int lbm_set_walls(lbm_ctx* ctx, int32_t box, const double* wall)
+int lbm_set_walls_kind(lbm_ctx* ctx, int32_t box, const double* wall, const int32_t* kind)
 {
-    if (!ctx || !wall || box < 0 || box >= int32_t(ctx->boxes.size())) return LBM_E_ARG;
+    if (!ctx || !wall || !kind || box < 0 || box >= int32_t(ctx->boxes.size())) return LBM_E_ARG;
     if (!(ctx->base.model & MODEL_WALLS)) return LBM_E_ARG;
+    if ((kind[0] != LBM_WALL_DIFFUSE && kind[0] != LBM_WALL_SPECULAR) ||
+        (kind[1] != LBM_WALL_DIFFUSE && kind[1] != LBM_WALL_SPECULAR))
+        return LBM_E_ARG;
     const int model = int(ctx->base.model & MODEL_BASE_MASK);
-    double dev[2 * Q];
+    double dev[2 * WALL_STRIDE];
     for (int w = 0; w < 2; ++w) {
         const double* u = wall + 4 * w;
         for (int k = 0; k < 4; ++k)
             if (!std::isfinite(u[k])) return LBM_E_DOMAIN;
         if (model != MODEL_ISO && !(u[3] > 0.0)) return LBM_E_DOMAIN;
         // the wall's equilibrium at unit density, as deviations f_w,q / w_q - 1
-        equilibrium_dev_f64(1.0, u[0], u[1], u[2], model == MODEL_ISO ? THETA0 : u[3], 1.0, model, dev + w * Q);
+        equilibrium_dev_f64(1.0, u[0], u[1], u[2], model == MODEL_ISO ? THETA0 : u[3], 1.0, model,
+                            dev + w * WALL_STRIDE);
         for (int q = 0; q < Q; ++q)
-            if (!(dev[w * Q + q] > -1.0) || !std::isfinite(dev[w * Q + q])) return LBM_E_DOMAIN;
+            if (!(dev[w * WALL_STRIDE + q] > -1.0) || !std::isfinite(dev[w * WALL_STRIDE + q])) return LBM_E_DOMAIN;
+        dev[w * WALL_STRIDE + Q] = kind[w] == LBM_WALL_SPECULAR ? 1.0 : 0.0;
     }
     HIPCHK(hipMemcpyAsync(ctx->boxes[box].wall_dev, dev, sizeof(dev), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return LBM_OK;
+}
+
+int lbm_set_walls(lbm_ctx* ctx, int32_t box, const double* wall)
+{
+    const int32_t diffuse[2] = {LBM_WALL_DIFFUSE, LBM_WALL_DIFFUSE};
+    return lbm_set_walls_kind(ctx, box, wall, diffuse);
 }
 
 int lbm_collide_host(int32_t precision, int32_t newton, uint32_t flags, double omega, const double* f_in,

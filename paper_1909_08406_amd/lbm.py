@@ -88,6 +88,7 @@ SIGNATURES = {
     "lbm_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(Info)]),
     "lbm_set_step_counter": (ctypes.c_int, [_vp, ctypes.c_uint32]),
     "lbm_set_walls": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
+    "lbm_set_walls_kind": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, ctypes.POINTER(ctypes.c_int32)]),
     "lbm_num_variants": (ctypes.c_int, []),
     "lbm_variant_desc": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_uint32)]),
@@ -218,13 +219,16 @@ class Context:
         _check(lib().lbm_get_populations(self.handle, _d(f)), "lbm_get_populations")
         return f
 
-    def set_walls(self, box, lower, upper):
-        """lbm_set_walls: (ux, uy, uz, theta) of the lower and the upper wall
-        of one box (theta absolute)."""
+    def set_walls(self, box, lower, upper, kinds=("diffuse", "diffuse")):
+        """lbm_set_walls_kind: (ux, uy, uz, theta) of the lower and the upper
+        wall of one box (theta absolute) and their kinds ("diffuse" or
+        "specular")."""
         w = np.ascontiguousarray(list(lower) + list(upper), dtype=np.float64)
         if w.size != 8:
             raise ValueError("two (ux, uy, uz, theta) expected")
-        _check(lib().lbm_set_walls(self.handle, int(box), _d(w)), "lbm_set_walls")
+        names = {"diffuse": 0, "specular": 1}
+        k = (ctypes.c_int32 * 2)(*[names[x] if isinstance(x, str) else int(x) for x in kinds])
+        _check(lib().lbm_set_walls_kind(self.handle, int(box), _d(w), k), "lbm_set_walls_kind")
 
     def set_populations(self, f):
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
