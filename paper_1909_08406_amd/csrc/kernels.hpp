@@ -613,12 +613,15 @@ __device__ __forceinline__ void step_node(const char* __restrict__ src, char* __
 
     R x[Q];
     T out[Q];
-    if constexpr (sizeof(T) == 2 && !SR && !(MODEL & (MODEL_ENTROPIC | MODEL_WALLS))) {
-        // 16-bit storage, round to nearest: the raw values are also kept two
-        // per 32-bit register and decoded again for the relaxation (fewer
-        // live registers through the equilibrium solve). Measured faster for
-        // round to nearest and slower with stochastic rounding, whose
-        // encoding adds its own live values.
+    // 16-bit storage: the raw values are also kept two per 32-bit register
+    // and decoded again for the relaxation (fewer live registers through the
+    // equilibrium solve). Measured faster for round to nearest, and with
+    // stochastic rounding for FP16 with the exact equilibrium (8.69 -> 8.60
+    // ms per 512^3 step); 1.5% slower for BF16 and for the series
+    // equilibrium with stochastic rounding, which keep the decoded values.
+    constexpr bool PACK = sizeof(T) == 2 && !(MODEL & (MODEL_ENTROPIC | MODEL_WALLS)) &&
+                          (!SR || (std::is_same<ST, StoreF16S>::value && (MODEL & MODEL_BASE_MASK) == MODEL_E2));
+    if constexpr (PACK) {
         constexpr int QP = (Q + 1) / 2;
         uint32_t pk[QP];
         static_for<Q>([&](auto qc) {
