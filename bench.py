@@ -58,9 +58,10 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(form):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
+def measured_traffic(form, block, hints):
+    """HBM bytes per launch of the launch variant (block size, cache hints)
+    of a form from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source; else None."""
     try:
         with open(COUNTERS) as fh:
             d = json.load(fh)
@@ -68,11 +69,11 @@ def measured_traffic(form):
         return None
     if d.get("source_sha256") != kernel_source_hash():
         return None
-    rec = d.get("forms", {}).get(form)
+    rec = d.get("forms", {}).get(form, {}).get("%d,%d" % (block, hints))
     if not rec:
         return None
     return {"fetch_bytes": rec["fetch_bytes"], "write_bytes": rec["write_bytes"],
-            "total_bytes": rec["fetch_bytes"] + rec["write_bytes"],
+            "total_bytes": rec["fetch_bytes"] + rec["write_bytes"], "kernel": rec["kernel"],
             "scale": d.get("scale"), "source": os.path.relpath(COUNTERS, ROOT)}
 
 
@@ -137,8 +138,13 @@ def time_form(lbm, torch, F, th, n, tau, form, steps, warmup, autotune):
     nodes = info["nodes"]
     ms_step = ms / steps
     bytes_launch = ALGO_VALUES_PER_NODE * lbm.ELEM_BYTES[storage] * nodes
+    # launch variant that was timed (the models other than E2 run 256 threads, no hints)
+    blk, hints = lbm.variant_desc(info["variant"])
+    if info["block_threads"] != blk:
+        blk, hints = info["block_threads"], 0
     return {
         "form": form,
+        "launch": [blk, hints],
         "ms_per_step": ms_step,
         "mlups": nodes * steps / (ms * 1e-3) / 1e6,
         "gbs": bytes_launch / (ms_step * 1e-3) / 1e9,
@@ -263,7 +269,7 @@ def main():
         print("# cpu baseline: %s" % cpu["sample"], file=sys.stderr, flush=True)
     by = {r["form"]: {k: r[k] for k in ("mlups", "gbs", "ms_per_step", "status", "shift_exp", "newton_iters",
                                         "tuning")} for r in runs}
-    traffic = measured_traffic(head["form"])
+    traffic = measured_traffic(head["form"], *head["launch"])
     out = {
         "metric": "MLUPS + achieved HBM GB/s, fused collide-stream, FP16-shifted vs FP32 storage",
         "value": head["mlups"],
