@@ -482,3 +482,43 @@ def test_pulse_96_vs_oracle(L, orc, storage, sr, tol):
     say("pulse 96^3 %s%s: normwise moment error %.2e (%.2e of the perturbation)"
         % (storage, "+SR" if sr else "", err, err * np.max(np.abs(m_ref)) / pert))
     assert err <= tol
+
+
+def test_padded_and_unpadded_boxes_in_one_context(L, orc):
+    """16-bit storage pads a box's q-block stride when the block is a
+    multiple of 1 MiB (64^3 cells in FP16: 2^20 bytes) and not otherwise
+    (32x32x64: 2^18 bytes). A context mixing both: populations written and
+    read back exactly in the host order; the batched schedule and graph
+    replays bit-identical to per-box launches; the padded box's moments
+    after 20 steps against the oracle (1e-5 normwise, FP16-shifted+SR)."""
+    boxes = [(64, 64, 64, 0.6), (32, 32, 64, 0.7), (16, 8, 4, 0.55)]
+    _, _, th = L.lattice()
+    fields = [wl.random_state(b[0], b[1], b[2], seed=90 + i, amp_u=0.01, amp_rho=2e-3, amp_theta=2e-3)
+              for i, b in enumerate(boxes)]
+    args = wl.concat(fields)
+    ctx = L.init(boxes, args[0], args[1], args[2], args[3], args[4] * th, storage="f16s", stochastic=True)
+    f0 = ctx.get_populations()
+    ctx.set_populations(f0)
+    assert np.array_equal(ctx.get_populations(), f0)
+    ctx.free()
+    out = {}
+    for name, tune in (("per_box", dict(schedule="per_box", graph_steps=0)),
+                       ("batched", dict(schedule="batched", graph_steps=0)),
+                       ("graph", dict(schedule="batched", graph_steps=4))):
+        ctx = L.init(boxes, args[0], args[1], args[2], args[3], args[4] * th, storage="f16s", stochastic=True)
+        ctx.set_tuning(**tune)
+        ctx.step(20)
+        out[name] = (ctx.get_populations(), ctx.moments())
+        assert ctx.status() == 0
+        ctx.free()
+    assert np.array_equal(out["per_box"][0], out["batched"][0])
+    assert np.array_equal(out["per_box"][0], out["graph"][0])
+    # the padded 64^3 box against the oracle
+    nx, ny, nz, tau = boxes[0]
+    F = fields[0]
+    f = orc.run(nx, ny, nz, 1 / tau, orc.init(nx, ny, nz, *F.absolute(th)), 20)
+    m_ref = orc.moment_fields(f)
+    m = out["per_box"][1][:, :2 * nx * ny * nz]
+    err = float(np.max(np.abs(m - m_ref)) / np.max(np.abs(m_ref)))
+    say("padded 64^3 box, FP16-shifted+SR, 20 steps: moment error %.2e" % err)
+    assert err <= 1e-5
