@@ -517,7 +517,8 @@ __device__ __forceinline__ void collide_encode(typename ST::R x[Q], typename ST:
             } else if constexpr (ST::shifted) {
                 out[q] = ST::encode_sr(y[q], rb);
             } else {
-                out[q] = sr_add(x[q], y[q], rb);  // stochastic rounding exists for FP32 only
+                // stochastic rounding exists for FP32 only; f = d + w where x holds d
+                out[q] = sr_add(DEV_IN_PLACE<R> ? x[q] + R(weight(q)) : x[q], y[q], rb);
             }
         } else {
             if constexpr (ST::shifted) out[q] = ST::encode(y[q]);
