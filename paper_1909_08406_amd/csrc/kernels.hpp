@@ -517,8 +517,7 @@ __device__ __forceinline__ void collide_encode(typename ST::R x[Q], typename ST:
             } else if constexpr (ST::shifted) {
                 out[q] = ST::encode_sr(y[q], rb);
             } else {
-                // stochastic rounding exists for FP32 only; f = d + w where x holds d
-                out[q] = sr_add(DEV_IN_PLACE<R> ? x[q] + R(weight(q)) : x[q], y[q], rb);
+                out[q] = sr_add(x[q], y[q], rb);  // stochastic rounding exists for FP32 only
             }
         } else {
             if constexpr (ST::shifted) out[q] = ST::encode(y[q]);
