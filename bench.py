@@ -9,7 +9,7 @@ autotuned (launch configuration), then a step is one launch of the fused
 kernel over all nodes, timed with HIP events on the context's stream; the
 inputs are resident in HBM before timing starts.
 
-Prints one JSON line. --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line. --gpus above 1 is refused: the library has no multi-GPU path.
 """
 import argparse
 import glob
@@ -224,7 +224,7 @@ DTYPE = {"f16s": "f16-shifted storage, f32 compute", "bf16s": "bf16-shifted stor
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch

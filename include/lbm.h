@@ -57,7 +57,7 @@ typedef enum {
     LBM_E_DOMAIN = -3,      /* unrealisable input: rho <= 0, theta <= 0 or non-finite field */
     LBM_E_NONFINITE = -4,   /* a step produced rho <= 0, theta <= 0 or a non-finite moment */
     LBM_E_HIP = -5,         /* a HIP runtime call failed */
-    LBM_E_UNSUPPORTED = -6  /* valid request this build or device cannot serve */
+    LBM_E_UNSUPPORTED = -6  /* valid request the library or device cannot serve */
 } lbm_error;
 
 /* How populations are held in device memory (arithmetic type in brackets). */
