@@ -312,10 +312,12 @@ int lbm_get_tuning(lbm_ctx *ctx, lbm_tuning *t);
 
 /*
  * Time every (variant, xcd_remap) pair with `reps` steps each on the
- * context's own boxes (with its current schedule) and keep the fastest. The held state is unchanged
- * (each timed launch reads the current buffer and writes the other one).
- * ms (optional) receives 2*lbm_num_variants() mean step times, index
- * 2*variant + xcd_remap; best (optional) the choice. Synchronous.
+ * context's own boxes (with its current schedule), in three interleaved
+ * rounds, and keep the pair whose fastest round is fastest. The held state
+ * is unchanged (each timed launch reads the current buffer and writes the
+ * other one). ms (optional) receives 2*lbm_num_variants() step times (the
+ * fastest round's mean), index 2*variant + xcd_remap; best (optional) the
+ * choice. Synchronous.
  */
 int lbm_autotune(lbm_ctx *ctx, int32_t reps, float *ms, lbm_tuning *best);
 

@@ -998,31 +998,44 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, float* ms, lbm_tuning* best)
     const int saved_v = ctx->variant;
     const uint32_t saved_x = ctx->base.xcd_remap;
     int rc = LBM_OK;
-    float best_ms = 0.f;
     lbm_tuning bt{saved_v, int32_t(saved_x), ctx->schedule, ctx->graph_steps};
-    for (int v = 0; v < NVARIANTS && rc == LBM_OK; ++v) {
-        for (int x = 0; x < 2 && rc == LBM_OK; ++x) {
-            ctx->variant = v;
-            ctx->base.xcd_remap = uint32_t(x);
-            // reads the current buffer, writes the other one, never flips:
-            // the held state is left unchanged
-            for (int r = -1; r < reps && rc == LBM_OK; ++r) {
-                if (r == 0 && hipEventRecord(e0, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
-                if (rc == LBM_OK) rc = enqueue_step(ctx, ctx->cur, ctx->steps_done, nullptr, ctx->stream);
+    // every configuration is timed once per round, the rounds interleaved,
+    // and keeps its fastest round (less bias from clock ramps and drift than
+    // timing each configuration once in a fixed order)
+    constexpr int ROUNDS = 3;
+    float tmin[2 * NVARIANTS];
+    for (int k = 0; k < 2 * NVARIANTS; ++k) tmin[k] = 0.f;
+    for (int round = 0; round < ROUNDS && rc == LBM_OK; ++round) {
+        for (int v = 0; v < NVARIANTS && rc == LBM_OK; ++v) {
+            for (int x = 0; x < 2 && rc == LBM_OK; ++x) {
+                ctx->variant = v;
+                ctx->base.xcd_remap = uint32_t(x);
+                // reads the current buffer, writes the other one, never flips:
+                // the held state is left unchanged
+                for (int r = -1; r < reps && rc == LBM_OK; ++r) {
+                    if (r == 0 && hipEventRecord(e0, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
+                    if (rc == LBM_OK) rc = enqueue_step(ctx, ctx->cur, ctx->steps_done, nullptr, ctx->stream);
+                }
+                if (rc == LBM_OK && hipEventRecord(e1, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
+                if (rc == LBM_OK && hipEventSynchronize(e1) != hipSuccess) rc = LBM_E_HIP;
+                float t = 0.f;
+                if (rc == LBM_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = LBM_E_HIP;
+                t /= float(reps);
+                if (rc == LBM_OK && (tmin[2 * v + x] == 0.f || t < tmin[2 * v + x])) tmin[2 * v + x] = t;
             }
-            if (rc == LBM_OK && hipEventRecord(e1, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
-            if (rc == LBM_OK && hipEventSynchronize(e1) != hipSuccess) rc = LBM_E_HIP;
-            float t = 0.f;
-            if (rc == LBM_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = LBM_E_HIP;
-            t /= float(reps);
+        }
+    }
+    float best_ms = 0.f;
+    for (int v = 0; v < NVARIANTS && rc == LBM_OK; ++v)
+        for (int x = 0; x < 2; ++x) {
+            const float t = tmin[2 * v + x];
             if (ms) ms[2 * v + x] = t;
-            if (rc == LBM_OK && (best_ms == 0.f || t < best_ms)) {
+            if (best_ms == 0.f || t < best_ms) {
                 best_ms = t;
                 bt.variant = v;
                 bt.xcd_remap = x;
             }
         }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != LBM_OK) {
