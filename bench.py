@@ -58,10 +58,10 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(form, block, hints):
-    """HBM bytes per launch of the launch variant (block size, cache hints)
-    of a form from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source; else None."""
+def measured_traffic(form, block, hints, xcd_remap):
+    """HBM bytes per launch of the launch variant (block size, cache hints,
+    XCD remap) of a form from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
     try:
         with open(COUNTERS) as fh:
             d = json.load(fh)
@@ -69,7 +69,7 @@ def measured_traffic(form, block, hints):
         return None
     if d.get("source_sha256") != kernel_source_hash():
         return None
-    rec = d.get("forms", {}).get(form, {}).get("%d,%d" % (block, hints))
+    rec = d.get("forms", {}).get(form, {}).get("%d,%d,%d" % (block, hints, xcd_remap))
     if not rec:
         return None
     return {"fetch_bytes": rec["fetch_bytes"], "write_bytes": rec["write_bytes"],
@@ -118,6 +118,7 @@ def time_form(lbm, torch, F, th, n, tau, form, steps, warmup, autotune):
         best, table = ctx.autotune(reps=3)
         tune = {"variant": best[0], "xcd_remap": best[1]}
     info = ctx.info()
+    tuning_now = ctx.tuning()
     if tune is not None:
         tune["block_threads"] = info["block_threads"]
     ctx.step(warmup)
@@ -144,7 +145,7 @@ def time_form(lbm, torch, F, th, n, tau, form, steps, warmup, autotune):
         blk, hints = info["block_threads"], 0
     return {
         "form": form,
-        "launch": [blk, hints],
+        "launch": [blk, hints, int(tuning_now["xcd_remap"])],
         "ms_per_step": ms_step,
         "mlups": nodes * steps / (ms * 1e-3) / 1e6,
         "gbs": bytes_launch / (ms_step * 1e-3) / 1e9,
