@@ -42,14 +42,16 @@ def _perturbed(orc, dims, seed, amp, model, field=1.0):
     ("f64", "thermal", 1e-3, 0.02, 1e-12),
     ("f32", "thermal", 1e-3, 1.0, 1e-5), ("f32", "thermal", 0.2, 1.0, 1e-5), ("f32", "isothermal", 0.2, 1.0, 1e-5),
     ("f32", "thermal", 1e-3, 0.02, 1e-5), ("f16s", "thermal", 1e-3, 0.02, 1e-5),
-    ("f16s", "thermal", 0.02, 0.02, 3e-5)])
+    ("f16s", "thermal", 0.02, 0.02, 3e-5), ("f16s", "isothermal", 0.02, 0.02, 3e-5),
+    ("bf16s", "thermal", 1e-3, 0.02, 8e-5)])
 def test_entropic_vs_oracle_far_from_equilibrium(L, orc, storage, model, amp, field, tol):
     """Ragged 13x7x5 box loaded with perturbed populations, 6 entropic steps
     at tau 0.505: amp 0.2 puts most nodes on the kernel's Newton-on-dH path;
     amp 1e-3 on a 0.02-scaled field keeps every node on its series path
     (FP16-shifted storage resolves deviations of that size; at amp 0.02
     its second-order closed form decides alpha, and the bar is three FP16
-    quanta of the deviation, 3e-5). The GPU holds
+    quanta of the deviation, 3e-5; BF16 keeps three mantissa bits fewer, so
+    its bar is eight times FP16's). The GPU holds
     post-collision values, so the oracle reproduces its sequence: stream (a
     step with omega = 0), 5 steps, then a collision. Moments normwise
     (1e-12 FP64, 1e-5 FP32 arithmetic) and populations within 10x that."""
@@ -106,13 +108,15 @@ def test_entropic_batched_and_graph_match_per_box(L):
     assert np.array_equal(out["per_box"], out["graph"])
 
 
-@pytest.mark.parametrize("storage,sr,tol", [("f64", False, 1e-7), ("f32", True, 1e-5), ("f16s", True, 1e-5)])
+@pytest.mark.parametrize("storage,sr,tol", [("f64", False, 1e-7), ("f32", True, 1e-5), ("f16s", True, 1e-5),
+                                            ("bf16s", True, 8e-5)])
 def test_entropic_close_to_bgk_on_resolved_flow(L, storage, sr, tol):
     """Standing wave 32x16x16 at amplitude A = 1e-3, tau 0.6, 200 steps. The
     departure from equilibrium is x ~ 1e-4 here and alpha = 2 + O(x), so the
     entropic step changes the effective viscosity by O(x) relative and the
     field by O(x) of A over a decay time: normwise 1e-7 in FP64 (measured
-    ~6e-9), and within the rounding of the reduced-precision forms."""
+    ~6e-9), and within the rounding of the reduced-precision forms (BF16:
+    eight times FP16's bar, for three mantissa bits fewer)."""
     nx, ny, nz, tau = 32, 16, 16, 0.6
     _, _, th = L.lattice()
     F = wl.standing_wave(nx, ny, nz, 1e-3)
