@@ -17,7 +17,8 @@
 #include <vector>
 
 #include "../../include/lbm.h"
-#include "kernels.hpp"
+#include "kernels_io.hpp"
+#include "step_launch.hpp"
 
 using namespace lbm;
 
@@ -48,12 +49,6 @@ struct BoxDev {
     uint64_t node0;   // index of the box's first node in the context
     double* wall_dev = nullptr;  // device: the box's two walls, 41 deviations and the kind each
 };
-
-// Block sizes of the step-kernel variants; the batched launch keeps one
-// (box, tile) list per block size.
-constexpr int NBLK = 4;
-constexpr int BLK_SIZES[NBLK] = {128, 256, 512, 1024};
-constexpr int blk_index(int blk) { return blk == 128 ? 0 : blk == 256 ? 1 : blk == 512 ? 2 : 3; }
 
 struct Layout {
     uint64_t elems = 0;      // elements per population buffer
@@ -234,47 +229,6 @@ int dispatch_storage(int storage, F&& f)
 
 uint32_t nblocks(uint64_t n) { return uint32_t((n + BLOCK - 1) / BLOCK); }
 
-// Step-kernel launch variants: block size and cache-policy hints. The
-// autotuner picks one per context (together with the XCD tile mapping).
-struct VariantDesc {
-    int blk;
-    int fl;
-};
-constexpr VariantDesc VARIANTS[] = {
-    {256, 0}, {256, FL_NT_LOAD | FL_NT_STORE}, {512, 0}, {128, 0}, {256, FL_NT_STORE}, {1024, 0},
-};
-constexpr int NVARIANTS = int(sizeof(VARIANTS) / sizeof(VARIANTS[0]));
-
-// Calls f(integral_constant<BLK>, integral_constant<FL>) for variant v.
-template <class F>
-int with_variant(int v, F&& f)
-{
-    using std::integral_constant;
-    switch (v) {
-        case 0: f(integral_constant<int, 256>{}, integral_constant<int, 0>{}); break;
-        case 1: f(integral_constant<int, 256>{}, integral_constant<int, FL_NT_LOAD | FL_NT_STORE>{}); break;
-        case 2: f(integral_constant<int, 512>{}, integral_constant<int, 0>{}); break;
-        case 3: f(integral_constant<int, 128>{}, integral_constant<int, 0>{}); break;
-        case 4: f(integral_constant<int, 256>{}, integral_constant<int, FL_NT_STORE>{}); break;
-        case 5: f(integral_constant<int, 1024>{}, integral_constant<int, 0>{}); break;
-        default: return LBM_E_ARG;
-    }
-    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
-}
-
-template <class F>
-int with_newton(int n, F&& f)
-{
-    using std::integral_constant;
-    switch (n) {
-        case 1: return f(integral_constant<int, 1>{});
-        case 2: return f(integral_constant<int, 2>{});
-        case 3: return f(integral_constant<int, 3>{});
-        case 4: return f(integral_constant<int, 4>{});
-        default: return LBM_E_ARG;
-    }
-}
-
 // Enqueue one step of every box from buffer `from` into the other buffer on
 // stream s. The stochastic-rounding step is `step`, plus *step_base when
 // step_base is not null (graph replays).
@@ -282,7 +236,7 @@ int enqueue_step(lbm_ctx* ctx, int from, uint32_t step, const uint32_t* step_bas
 {
 #if defined(LBM_HOST_CHECK)
     // host-code check build (the sanitizer on the host code, no device):
-    // the step kernels are not instantiated and a step is refused
+    // the step kernels are not built and a step is refused
     (void)ctx;
     (void)from;
     (void)step;
@@ -290,79 +244,48 @@ int enqueue_step(lbm_ctx* ctx, int from, uint32_t step, const uint32_t* step_bas
     (void)s;
     return LBM_E_UNSUPPORTED;
 #else
-    return dispatch_storage(ctx->storage, [&](auto st) {
-        using ST = decltype(st);
-        using T = typename ST::T;
-        const T* in = reinterpret_cast<const T*>(ctx->buf(from));
-        T* out = reinterpret_cast<T*>(ctx->buf(1 - from));
-        // stochastic rounding exists for the FP32-arithmetic forms whose
-        // rounding is coarse: FP32 of f, FP16 and BF16 of the shift
-        constexpr bool has_sr = std::is_same<ST, StoreF32>::value || std::is_same<ST, StoreF16S>::value ||
-                                std::is_same<ST, StoreBF16S>::value;
-        return with_newton(ctx->newton, [&](auto nw) {
-            constexpr int NEWTON = decltype(nw)::value;
-            auto launch = [&](auto sr, auto model, auto blk, auto fl) {
-                constexpr bool SR = decltype(sr)::value;
-                constexpr int MODEL = decltype(model)::value;
-                constexpr int BLK = decltype(blk)::value;
-                constexpr int FL = decltype(fl)::value;
-                if (ctx->schedule == LBM_SCHEDULE_BATCHED) {
-                    const int i = blk_index(BLK);
-                    hipLaunchKernelGGL((k_step_batch<ST, NEWTON, BLK, FL, SR, MODEL>), dim3(uint32_t(ctx->L.ntiles[i])),
-                                       dim3(BLK), 0, s, in, out, ctx->table, ctx->tiles[i], ctx->base.xcd_remap, step,
-                                       step_base);
-                } else {
-                    for (const BoxDev& b : ctx->boxes) {
-                        StepParams p = ctx->params(b);
-                        p.step = step;
-                        p.step_base = step_base;
-                        hipLaunchKernelGGL((k_step<ST, NEWTON, BLK, FL, SR, MODEL>),
-                                           dim3(uint32_t((b.nodes + BLK - 1) / BLK)), dim3(BLK), 0, s,
-                                           in + b.offset, out + b.offset, p);
-                    }
-                }
-            };
-            auto go = [&](auto sr) -> int {
-                using std::integral_constant;
-                if (ctx->base.model != MODEL_E2) {
-                    // the other models run the default launch shape
-                    const integral_constant<int, 256> blk;
-                    const integral_constant<int, 0> fl;
-                    switch (ctx->base.model) {
-                        case MODEL_ISO: launch(sr, integral_constant<int, MODEL_ISO>{}, blk, fl); break;
-                        case MODEL_SERIES: launch(sr, integral_constant<int, MODEL_SERIES>{}, blk, fl); break;
-                        case MODEL_E2 | MODEL_ENTROPIC:
-                            launch(sr, integral_constant<int, MODEL_E2 | MODEL_ENTROPIC>{}, blk, fl);
-                            break;
-                        case MODEL_ISO | MODEL_ENTROPIC:
-                            launch(sr, integral_constant<int, MODEL_ISO | MODEL_ENTROPIC>{}, blk, fl);
-                            break;
-                        case MODEL_E2 | MODEL_WALLS:
-                            launch(sr, integral_constant<int, MODEL_E2 | MODEL_WALLS>{}, blk, fl);
-                            break;
-                        case MODEL_ISO | MODEL_WALLS:
-                            launch(sr, integral_constant<int, MODEL_ISO | MODEL_WALLS>{}, blk, fl);
-                            break;
-                        case MODEL_E2 | MODEL_ENTROPIC | MODEL_WALLS:
-                            launch(sr, integral_constant<int, MODEL_E2 | MODEL_ENTROPIC | MODEL_WALLS>{}, blk, fl);
-                            break;
-                        case MODEL_ISO | MODEL_ENTROPIC | MODEL_WALLS:
-                            launch(sr, integral_constant<int, MODEL_ISO | MODEL_ENTROPIC | MODEL_WALLS>{}, blk, fl);
-                            break;
-                        default: return LBM_E_ARG;
-                    }
-                    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
-                }
-                return with_variant(ctx->variant, [&](auto blk, auto fl) {
-                    launch(sr, integral_constant<int, MODEL_E2>{}, blk, fl);
-                });
-            };
-            if constexpr (has_sr) {
-                if (ctx->stochastic) return go(std::true_type{});
-            }
-            return go(std::false_type{});
-        });
-    });
+    StepLaunch L{};
+    L.in = ctx->buf(from);
+    L.out = ctx->buf(1 - from);
+    L.newton = ctx->newton;
+    L.schedule = ctx->schedule;
+    L.variant = ctx->variant;
+    L.model = ctx->base.model;
+    L.xcd_remap = ctx->base.xcd_remap;
+    L.step = step;
+    L.step_base = step_base;
+    L.stream = s;
+    L.table = ctx->table;
+    for (int i = 0; i < NBLK; ++i) {
+        L.tiles[i] = ctx->tiles[i];
+        L.ntiles[i] = ctx->L.ntiles[i];
+    }
+    std::vector<StepParams> params;
+    std::vector<uint64_t> offset, nodes;
+    if (ctx->schedule != LBM_SCHEDULE_BATCHED) {
+        for (const BoxDev& b : ctx->boxes) {
+            params.push_back(ctx->params(b));
+            offset.push_back(b.offset);
+            nodes.push_back(b.nodes);
+        }
+        L.nboxes = int(ctx->boxes.size());
+        L.params = params.data();
+        L.offset = offset.data();
+        L.nodes = nodes.data();
+    }
+    // stochastic rounding exists for the FP32-arithmetic forms whose
+    // rounding is coarse: FP32 of f, FP16 and BF16 of the shift
+    const bool sr = ctx->stochastic;
+    int rc;
+    switch (ctx->storage) {
+        case LBM_F64: rc = enqueue_step_f64(L); break;
+        case LBM_F32: rc = sr ? enqueue_step_f32_sr(L) : enqueue_step_f32(L); break;
+        case LBM_F32_SHIFT: rc = enqueue_step_f32s(L); break;
+        case LBM_F16_SHIFT: rc = sr ? enqueue_step_f16s_sr(L) : enqueue_step_f16s(L); break;
+        case LBM_BF16_SHIFT: rc = sr ? enqueue_step_bf16s_sr(L) : enqueue_step_bf16s(L); break;
+        default: rc = LBM_E_ARG; break;
+    }
+    return rc;
 #endif
 }
 
