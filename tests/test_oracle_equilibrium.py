@@ -171,6 +171,89 @@ def test_series_equilibrium_momentum_error_is_anisotropic_cubic(orc):
     assert np.max(np.abs(f @ c - u)) < 1e-12
 
 
+# Exact moments of E1 as printed (Sec. V: the series f~ times the cubic
+# velocity polynomial with A1, A2 of M2, M2'). With xi = u.c/theta and the
+# lattice moments of f~ written through the error terms
+#   <c_a c_b> = rho theta delta_ab,
+#   <c_x^4> = rho theta^2 (3 + 5 M2 - 2 M2'),  <c_x^2 c_y^2> = rho theta^2 (1 + M2'),
+#   <c^2 c_x^2 c_y^2> = 7 rho theta^3 (1 + M3'),  <c^6> = 105 rho theta^3 (1 + M3),
+# summing the polynomial term by term gives (derived by hand; odd terms of
+# f~ vanish):
+#   j_a   = rho u_a + rho u_a u^2 [3 (1 + M2') + A2 - 5 A1 (1 + M2)] / (6 theta)
+#           + 5 rho (M2 - M2') u_a^3 / (6 theta),
+#   P_ab  = rho theta d_ab + rho u_a u_b (1 + M2')
+#           + rho u^2 d_ab [M2' - 2 A1/3 - 5 A1 M2/3] / 2 + 5 rho (M2 - M2') u_a^2 d_ab / 2,
+#   <c_a c^2> = 5 rho theta u_a (1 + M2)
+#           + rho u^2 u_a [21 (1 + M3') + 5 A2 (1 + M2) - 35 A1 (1 + M3)] / 6
+#           + 35 rho (M3 - M3') u_a^3 / 6.
+# A2 enters only the odd moments, and there only through u^2 u_a: these are
+# the checks that see its M2 and M2' terms away from theta0 (at theta0 all
+# four error terms vanish).
+def _e1_closed_forms(rho, u, theta, m):
+    M2, M2p, M3, M3p = m
+    A1 = 2.5 * M2 / (1.0 + 2.5 * M2)
+    A2 = 5.0 * A1 * (1.0 - M2) - (3.0 + M2p - 5.0 * M2)
+    u2 = u @ u
+    j = rho * u + rho * u * u2 * (3 * (1 + M2p) + A2 - 5 * A1 * (1 + M2)) / (6 * theta) \
+        + 5 * rho * (M2 - M2p) * u ** 3 / (6 * theta)
+    P = rho * theta * np.eye(3) + rho * np.outer(u, u) * (1 + M2p) \
+        + np.eye(3) * (0.5 * rho * u2 * (M2p - 2 * A1 / 3 - 5 * A1 * M2 / 3)) \
+        + np.diag(2.5 * rho * (M2 - M2p) * u ** 2)
+    q = 5 * rho * theta * u * (1 + M2) + rho * u2 * u * (21 * (1 + M3p) + 5 * A2 * (1 + M2) - 35 * A1 * (1 + M3)) / 6 \
+        + 35 * rho * (M3 - M3p) * u ** 3 / 6
+    return j, P, q
+
+
+def _e1_cases(seed, n):
+    rng = np.random.default_rng(seed)
+    for _ in range(n):
+        rho = rng.uniform(0.5, 2.0)
+        u = rng.uniform(-0.15, 0.15, 3)
+        eta = rng.choice([-1, 1]) * rng.uniform(0.02, 0.12)  # away from theta0
+        yield rho, u, eta
+
+
+def test_series_equilibrium_moments_match_closed_forms_away_from_theta0(orc):
+    """Momentum, pressure tensor and energy flux <f, c_a c^2> of E1 equal
+    the closed forms above for random rho, u and eta != 0 (Sec. V)."""
+    c, w, t0 = orc.lattice()
+    c2 = (c ** 2).sum(1)
+    for rho, u, eta in _e1_cases(seed=21, n=40):
+        th = t0 * (1 + eta)
+        f = orc.equilibrium_series(rho, u, th)
+        j, P, q = _e1_closed_forms(rho, u, th, orc.series_errors(eta))
+        # relative to the size of each moment (measured: <= 1.4e-15)
+        um = np.max(np.abs(u))
+        assert np.max(np.abs(f @ c - j)) <= 3e-15 * rho * um, (rho, u, eta)
+        assert np.max(np.abs(np.einsum("q,qa,qb->ab", f, c, c) - P)) <= 3e-15 * rho * th, (rho, u, eta)
+        assert np.max(np.abs((f * c2) @ c - q)) <= 3e-15 * 5 * rho * th * um, (rho, u, eta)
+
+
+def test_series_equilibrium_closed_forms_see_a2_away_from_theta0(orc):
+    """The closed-form check resolves A2's M2 and M2' terms: moving A2 by
+    2 M2' (the slip 3 - M2' for 3 + M2') moves the predicted momentum and
+    energy flux by far more than the tolerance of the check, and the
+    oracle's E1 agrees with the printed A2 only."""
+    c, w, t0 = orc.lattice()
+    c2 = (c ** 2).sum(1)
+    rho, u, eta = 1.1, np.array([0.1, -0.06, 0.03]), 0.06
+    th = t0 * (1 + eta)
+    m = orc.series_errors(eta)
+    f = orc.equilibrium_series(rho, u, th)
+    j, _, q = _e1_closed_forms(rho, u, th, m)
+    M2, M2p, M3, M3p = m
+    # A2 shifted by -2 M2' enters j as rho u_a u^2 dA2 / (6 theta) and q as 5 rho u^2 u_a dA2 (1 + M2) / 6
+    dA2 = -2 * M2p
+    j_slip = j + rho * u * (u @ u) * dA2 / (6 * th)
+    q_slip = q + 5 * rho * (u @ u) * u * dA2 * (1 + M2) / 6
+    um = np.max(np.abs(u))
+    tol_j, tol_q = 3e-15 * rho * um, 3e-15 * 5 * rho * th * um
+    assert abs(M2p) > 1e-3
+    assert np.max(np.abs(f @ c - j)) <= tol_j and np.max(np.abs((f * c2) @ c - q)) <= tol_q
+    assert np.max(np.abs(f @ c - j_slip)) > 1e4 * tol_j
+    assert np.max(np.abs((f * c2) @ c - q_slip)) > 1e4 * tol_q
+
+
 # ---------------------------------------------------------------------------
 # Isothermal equilibrium: the same H-minimiser with the mass and momentum
 # constraints only (Sec. V; used by the paper's isothermal acoustic pulse,
