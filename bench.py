@@ -44,9 +44,16 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-box batch measurement")
     ap.add_argument("--batch-forms", default="f16s+sr,f32")
-    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--batch-steps", type=int, default=100, help="eager steps timed for the batch")
+    ap.add_argument("--batch-graph-steps", type=int, default=1000,
+                    help="steps of the captured graph the batch is timed with (one replay)")
     ap.add_argument("--copy-reference", type=float, default=0.0, metavar="GIB",
                     help="only time a plain device-to-device copy of GIB GiB (HBM counter reference)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="only print a markdown summary of rocprofv3 --pmc outputs (*_counter_collection.csv "
+                         "under each DIR): per step-kernel instance, the median of each counter over its dispatches "
+                         "and the figures derived from them")
+    ap.add_argument("--kernel-filter", default="k_step", help="kernels summarized by --summarize-counters")
     return ap.parse_args()
 
 
@@ -95,6 +102,79 @@ def copy_reference(torch, gib, reps=5):
                       "gbs_read_plus_write": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
 
 
+# MI355X: 256 CUs of 4 SIMDs in 8 XCDs (GRBM_GUI_ACTIVE is summed over the XCDs)
+CUS, SIMDS_PER_CU, XCDS = 256, 4, 8
+
+
+def summarize_counters(dirs, kernel_filter):
+    """Median per dispatch of every counter of each matching kernel instance
+    (rocprofv3 --pmc CSVs), with derived figures: instructions per wavefront,
+    the clock (GRBM_GUI_ACTIVE per XCD over the dispatch duration), VALU issue
+    share (a wave64 VALU instruction issues over 2 cycles of a SIMD), mean
+    waves per SIMD (SQ_WAVE_CYCLES counts 4-cycle units), L2 hit rate."""
+    import csv
+    import statistics
+    rows = []
+    for d in dirs:
+        for path in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+            with open(path) as fh:
+                rows += list(csv.DictReader(fh))
+    per = {}
+    for r in rows:
+        if kernel_filter not in r["Kernel_Name"]:
+            continue
+        k = r["Kernel_Name"].split("(")[0]
+        disp = per.setdefault(k, {}).setdefault(r["Dispatch_Id"], {})
+        disp[r["Counter_Name"]] = float(r["Counter_Value"])
+        disp["_ns"] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        disp["_vgpr"] = r.get("VGPR_Count")
+    out = []
+    for k, disps in sorted(per.items()):
+        names = sorted({c for d in disps.values() for c in d if not c.startswith("_")})
+        med = {c: statistics.median(d[c] for d in disps.values() if c in d) for c in names}
+        ns = statistics.median(d["_ns"] for d in disps.values())
+        out.append("### `%s`" % k)
+        out.append("")
+        out.append("%d dispatches, median duration %.3f ms" % (len(disps), ns * 1e-6))
+        out.append("")
+        out.append("| counter | median per dispatch |")
+        out.append("|---|---|")
+        for c in names:
+            out.append("| %s | %.6g |" % (c, med[c]))
+        derived = []
+        w = med.get("SQ_WAVES")
+        gui = med.get("GRBM_GUI_ACTIVE")
+        if w:
+            for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_INSTS_LDS"):
+                if c in med:
+                    derived.append(("%s per wavefront" % c, med[c] / w))
+        if gui:
+            cyc = gui / XCDS
+            derived.append(("clock (GHz)", cyc / ns))
+            simds = CUS * SIMDS_PER_CU
+            if "SQ_INSTS_VALU" in med:
+                derived.append(("VALU issue share (2 cycles per wave64 instruction)", 2 * med["SQ_INSTS_VALU"] / (simds * cyc)))
+            if "SQ_ACTIVE_INST_VALU" in med:
+                derived.append(("SQ_ACTIVE_INST_VALU per SIMD-cycle", med["SQ_ACTIVE_INST_VALU"] / (simds * cyc)))
+            if "SQ_WAVE_CYCLES" in med:
+                derived.append(("mean waves per SIMD (SQ_WAVE_CYCLES x 4)", 4 * med["SQ_WAVE_CYCLES"] / (simds * cyc)))
+            for c in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VMEM"):
+                if c in med and "SQ_WAVE_CYCLES" in med:
+                    derived.append(("%s / SQ_WAVE_CYCLES" % c, med[c] / med["SQ_WAVE_CYCLES"]))
+            if "TA_TA_BUSY_sum" in med:
+                derived.append(("TA busy share (TA_TA_BUSY_sum per TA-cycle)", med["TA_TA_BUSY_sum"] / (CUS * cyc)))
+        if "TCC_HIT_sum" in med and "TCC_MISS_sum" in med:
+            derived.append(("L2 hit rate", med["TCC_HIT_sum"] / max(1.0, med["TCC_HIT_sum"] + med["TCC_MISS_sum"])))
+        if derived:
+            out.append("")
+            out.append("| derived | value |")
+            out.append("|---|---|")
+            for name, v in derived:
+                out.append("| %s | %.4g |" % (name, v))
+        out.append("")
+    print("\n".join(out))
+
+
 def parse_form(form):
     """'storage[+sr][+e1][+elbm][+walls]': storage form, stochastic rounding,
     series equilibrium E1 instead of the entropic E2, entropic path length,
@@ -106,7 +186,7 @@ def parse_form(form):
     return storage, "sr" in flags, "e1" in flags, "elbm" in flags, "walls" in flags
 
 
-def time_form(lbm, torch, F, th, n, tau, form, steps, warmup, autotune):
+def time_form(lbm, torch, F, th, n, tau, form, steps, warmup, autotune, pattern=False):
     storage, sr, e1, elbm, walls = parse_form(form)
     stream = torch.cuda.Stream()
     t0 = time.time()
@@ -133,6 +213,17 @@ def time_form(lbm, torch, F, th, n, tau, form, steps, warmup, autotune):
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
     status = ctx.status()
+    ms_pattern = None
+    if pattern:
+        # the step's access pattern alone: collisionless streaming in the same
+        # context, launch variant and tile mapping
+        ctx.stream_free(warmup)
+        ctx.synchronize()
+        start.record(stream)
+        ctx.stream_free(steps)
+        end.record(stream)
+        end.synchronize()
+        ms_pattern = start.elapsed_time(end) / steps
     ctx.free()
     del ctx
     torch.cuda.empty_cache()
@@ -156,13 +247,16 @@ def time_form(lbm, torch, F, th, n, tau, form, steps, warmup, autotune):
         "shift_exp": info["shift_exp"],
         "newton_iters": info["newton_iters"],
         "tuning": tune,
+        "ms_pattern": ms_pattern,
     }
 
 
-def time_batch(lbm, torch, form, steps, warmup, autotune):
+def time_batch(lbm, torch, form, steps, graph_steps, warmup, autotune):
     """The 256-box batch of uneven periodic standing-wave boxes (edges from
     {16, 24, 32, 48, 64, 96}, seed 0) in one context: one launch per step
-    over every (box, tile), eager and replayed from captured graphs."""
+    over every (box, tile), timed eager (`steps` steps) and as one replay of
+    a captured graph of `graph_steps` steps (after one untimed replay that
+    also captures it)."""
     from paper_1909_08406_amd import workloads as wl
 
     storage, sr, e1, elbm, walls = parse_form(form)
@@ -177,19 +271,21 @@ def time_batch(lbm, torch, form, steps, warmup, autotune):
         ctx.autotune(reps=3)
     nodes = ctx.info()["nodes"]
     out = {"nodes": nodes, "tuning": ctx.tuning()}
-    for mode, g in (("eager", 0), ("graph", 10)):
+    for mode, g in (("eager", 0), ("graph", graph_steps)):
         ctx.set_tuning(graph_steps=g)
+        n = steps if g == 0 else g
         ctx.step(max(warmup, g))
         ctx.synchronize()
         start = torch.cuda.Event(enable_timing=True)
         end = torch.cuda.Event(enable_timing=True)
         start.record(stream)
-        ctx.step(steps)
+        ctx.step(n)
         end.record(stream)
         end.synchronize()
-        ms = start.elapsed_time(end) / steps
+        ms = start.elapsed_time(end) / n
         bytes_launch = ALGO_VALUES_PER_NODE * lbm.ELEM_BYTES[storage] * nodes
-        out[mode] = {"ms_per_step": ms, "mlups": nodes / (ms * 1e-3) / 1e6, "gbs": bytes_launch / (ms * 1e-3) / 1e9}
+        out[mode] = {"ms_per_step": ms, "mlups": nodes / (ms * 1e-3) / 1e6, "gbs": bytes_launch / (ms * 1e-3) / 1e9,
+                     "steps_timed": n, "graph_steps": g}
     out["status"] = ctx.status()
     ctx.free()
     torch.cuda.empty_cache()
@@ -218,12 +314,25 @@ def cpu_baseline(args):
     }
 
 
+def pattern_ceiling(r):
+    """The step's memory access pattern alone (lbm_stream_free in the same
+    context and launch shape): its rate, and the step's time over it."""
+    if r.get("ms_pattern") is None:
+        return None
+    gbs = r["bytes_per_launch"] / (r["ms_pattern"] * 1e-3) / 1e9
+    return {"kernel": "lbm::k_stream_free", "ms_per_step": r["ms_pattern"], "achieved": gbs,
+            "frac": gbs / HBM_PEAK_GBS, "step_over_pattern": r["ms_per_step"] / r["ms_pattern"]}
+
+
 DTYPE = {"f16s": "f16-shifted storage, f32 compute", "bf16s": "bf16-shifted storage, f32 compute",
          "f32": "f32", "f32s": "f32-shifted storage, f32 compute", "f64": "f64"}
 
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.kernel_filter)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -243,20 +352,27 @@ def main():
     F = wl.gaussian_pulse(n, eps=1e-3, b=8.0)
     print("# fields %d^3 generated in %.1f s" % (n, time.time() - t0), file=sys.stderr, flush=True)
     runs = []
-    for form in args.forms.split(","):
-        r = time_form(lbm, torch, F, th, n, args.tau, form, args.steps, args.warmup, not args.no_autotune)
+    for i, form in enumerate(args.forms.split(",")):
+        r = time_form(lbm, torch, F, th, n, args.tau, form, args.steps, args.warmup, not args.no_autotune,
+                      pattern=(i == 0))
         print("# %s: %.3f ms/step, %.0f MLUPS, %.0f GB/s (init %.1f s, tuning %s)"
               % (form, r["ms_per_step"], r["mlups"], r["gbs"], r["init_s"], r["tuning"]), file=sys.stderr,
               flush=True)
+        if r["ms_pattern"] is not None:
+            pc = pattern_ceiling(r)
+            print("# %s access pattern alone (free streaming): %.3f ms/step, %.0f GB/s; step / pattern %.3f"
+                  % (form, pc["ms_per_step"], pc["achieved"], pc["step_over_pattern"]), file=sys.stderr, flush=True)
         runs.append(r)
     del F
     batch = None
     if not args.no_batch:
         batch = {"workload": "256 periodic standing-wave boxes, edges from {16,24,32,48,64,96}, k 1..4, "
-                             "tau U[0.51,1), amplitude 10^U[-4,-2], seed 0; one launch per step over all boxes",
+                             "tau U[0.51,1), amplitude 10^U[-4,-2], seed 0; one launch per step over all boxes; "
+                             "'graph' is one replay of a captured %d-step graph" % args.batch_graph_steps,
                  "forms": {}}
         for form in args.batch_forms.split(","):
-            r = time_batch(lbm, torch, form, args.batch_steps, args.warmup, not args.no_autotune)
+            r = time_batch(lbm, torch, form, args.batch_steps, args.batch_graph_steps, args.warmup,
+                           not args.no_autotune)
             batch["nodes"] = r.pop("nodes")
             batch["forms"][form] = r
             print("# batch %s: eager %.3f ms/step %.0f MLUPS %.0f GB/s; graph %.3f ms/step %.0f MLUPS %.0f GB/s (%s)"
@@ -294,12 +410,18 @@ def main():
                      "traffic": traffic["total_bytes"] / (head["ms_per_step"] * 1e-3) / 1e9 if traffic else None,
                      "traffic_bytes_per_launch": traffic,
                      "kernel": "lbm::k_step (%s)" % head["form"],
-                     "algorithmic_bytes_per_launch": head["bytes_per_launch"]},
+                     "algorithmic_bytes_per_launch": head["bytes_per_launch"],
+                     "pattern_ceiling": pattern_ceiling(head)},
         "cpu_baseline": cpu,
         "batch": batch,
     }
+    # FP32 storage that meets the thermal-mode accuracy bar is the one with
+    # stochastic rounding (round to nearest biases the slow entropy mode)
+    if "f32+sr" in by:
+        out["speedup_vs_f32"] = head["mlups"] / by["f32+sr"]["mlups"]
+        out["speedup_vs_f32_form"] = "f32+sr"
     if "f32" in by:
-        out["speedup_vs_f32"] = head["mlups"] / by["f32"]["mlups"]
+        out["speedup_vs_f32_round_to_nearest"] = head["mlups"] / by["f32"]["mlups"]
     print(json.dumps(out), flush=True)
 
 

@@ -213,6 +213,19 @@ int lbm_init_device(lbm_ctx **out, const lbm_box *boxes, int32_t nboxes, const l
  */
 int lbm_step(lbm_ctx *ctx, int32_t n);
 
+/*
+ * n >= 0 collisionless streaming steps (free flight): every population moves
+ * along its link unchanged, i.e. the update of Sec. II without the collision
+ * term (the free-molecular limit). The held values are permuted exactly
+ * (no rounding, any storage form), and mass, momentum and energy are kept.
+ * It runs the step kernel's pull addressing, loads and stores in the
+ * context's launch variant and tile mapping, so its rate is the ceiling of
+ * the step's memory access pattern. Queued on the context stream; the
+ * stochastic-rounding step counter is not advanced. Periodic boxes only:
+ * LBM_E_UNSUPPORTED with LBM_FLAG_WALLS. Errors: LBM_E_ARG, LBM_E_HIP.
+ */
+int lbm_stream_free(lbm_ctx *ctx, int32_t n);
+
 /* Wait for all work queued on the context stream. */
 int lbm_synchronize(lbm_ctx *ctx);
 
@@ -320,6 +333,58 @@ int lbm_get_tuning(lbm_ctx *ctx, lbm_tuning *t);
  * choice. Synchronous.
  */
 int lbm_autotune(lbm_ctx *ctx, int32_t reps, float *ms, lbm_tuning *best);
+
+/* lbm_autotune_ex flags */
+#define LBM_TUNE_SCHEDULE 1u /* also choose the schedule (contexts with several boxes) */
+#define LBM_TUNE_GRAPH 2u    /* also choose graph_steps among 0 (eager), 16 and 64 */
+#define LBM_TUNE_CACHE 4u    /* take the choice from the tuning cache when it holds the context's key,
+                                and record a new choice there */
+
+/* Outcome of lbm_autotune_ex. */
+typedef struct {
+    lbm_tuning best;    /* the configuration now in use by the context */
+    float best_ms;      /* its measured mean time per step (0 when taken from the cache) */
+    int32_t from_cache; /* 1 when the choice came from the cache and nothing was timed */
+    int32_t timed;      /* number of configurations timed (each in three rounds) */
+} lbm_tune_result;
+
+/*
+ * Autotuner with a wider search and a cache (the tile shape, cache hints
+ * and tile-to-XCD mapping of the step kernel, then optionally the schedule
+ * and the graph length). Every (variant, xcd_remap) pair is timed with the
+ * context's schedule and eager launches as in lbm_autotune; with
+ * LBM_TUNE_SCHEDULE the two schedules, then with LBM_TUNE_GRAPH eager
+ * launches against replays of captured 16- and 64-step graphs, are timed
+ * with the chosen pair. Within 0.5% of the fastest, the configuration with
+ * the XCD remap on (no HBM traffic beyond the algorithmic bytes), the
+ * current schedule and eager launches are preferred. Timed launches never
+ * change the held state. The choice is applied to the context.
+ * With LBM_TUNE_CACHE the choice is looked up first under the context's
+ * key (device architecture, storage, model and rounding flags, Newton
+ * steps, the search flags and the box shapes), and a new choice is stored
+ * under it; a hit times nothing. ms (optional) receives the
+ * 2*lbm_num_variants() variant/remap times as in lbm_autotune (zeros for a
+ * cache hit and for variants that a model does not use); res (optional)
+ * the outcome. Synchronous. Errors: LBM_E_ARG (reps < 1, unknown flag),
+ * LBM_E_HIP.
+ */
+int lbm_autotune_ex(lbm_ctx *ctx, int32_t reps, uint32_t flags, float *ms, lbm_tune_result *res);
+
+/*
+ * Back the tuning cache with a text file (one line per key: key, variant,
+ * xcd_remap, schedule, graph_steps): its entries are loaded now (malformed
+ * lines are skipped; the file is created if missing) and every new choice is
+ * appended. NULL: keep the cache in this process only. The cache is shared
+ * by every context of the process and thread-safe.
+ * Errors: LBM_E_ARG (file cannot be opened). No device needed.
+ */
+int lbm_tune_cache_file(const char *path);
+
+/* Forget every cached choice held in this process (a backing file is kept). */
+int lbm_tune_cache_clear(void);
+
+/* Number of choices held in the tuning cache of this process. */
+int lbm_tune_cache_count(void);
 
 /* The hipStream_t the context queues its work on. */
 void *lbm_stream(lbm_ctx *ctx);

@@ -627,6 +627,7 @@ struct StoreF64 {
     using R = double;
     static constexpr bool shifted = false;
     static constexpr bool unit_scale = true;
+    static constexpr float SAT = 0.0f;  // no saturation
     __device__ static R decode(T v) { return v; }
     __device__ static T encode(R v) { return v; }
     __device__ static R load(const T* p) { return *p; }
@@ -638,6 +639,7 @@ struct StoreF32 {
     using R = float;
     static constexpr bool shifted = false;
     static constexpr bool unit_scale = true;
+    static constexpr float SAT = 0.0f;  // no saturation
     __device__ static R decode(T v) { return v; }
     __device__ static T encode(R v) { return v; }
     __device__ static R load(const T* p) { return *p; }
@@ -650,6 +652,7 @@ struct StoreF32S {
     using R = float;
     static constexpr bool shifted = true;
     static constexpr bool unit_scale = true;
+    static constexpr float SAT = 0.0f;  // no saturation
     __device__ static R decode(T v) { return v; }
     __device__ static T encode(R v) { return v; }
     __device__ static R load(const T* p) { return *p; }
@@ -678,7 +681,10 @@ struct StoreF16S {
     // Two values with the two 16-bit halves of r: the random bits are added
     // below the kept mantissa and the pair is converted with round toward
     // zero in one instruction (the same rounding as encode_sr in the normal
-    // FP16 range).
+    // FP16 range). Round toward zero saturates at +-65504 where rounding up
+    // would leave the FP16 range; a stored magnitude of SAT is therefore
+    // taken as having left the range when it is read back (the next step,
+    // lbm_totals), and flagged as a non-finite result.
     __device__ static void encode_sr2(R a, R b, uint32_t r, T& oa, T& ob)
     {
         const float ra = __uint_as_float(__float_as_uint(a) + (r & 0x1fffu));
@@ -687,6 +693,7 @@ struct StoreF16S {
         oa = h[0];
         ob = h[1];
     }
+    static constexpr float SAT = 65504.0f;  // largest finite FP16
     __device__ static R load(const T* p) { return float(*p); }
     __device__ static void store(T* p, R v) { *p = _Float16(v); }
 };
@@ -721,12 +728,14 @@ struct StoreBF16S {
     __device__ static T encode_sr(R v, uint32_t r) { return __bf16(sr_truncate(v, r, 16)); }
     // Two values with the two 16-bit halves of r: the random bits are added
     // below the kept mantissa and the upper halves are the result.
+    // (BF16 keeps the FP32 exponent range: no overflow beyond FP32's own.)
     __device__ static void encode_sr2(R a, R b, uint32_t r, T& oa, T& ob)
     {
         const uint32_t ua = __float_as_uint(a) + (r & 0xffffu), ub = __float_as_uint(b) + (r >> 16);
         oa = __builtin_bit_cast(T, uint16_t(ua >> 16));
         ob = __builtin_bit_cast(T, uint16_t(ub >> 16));
     }
+    static constexpr float SAT = 0.0f;  // no saturation
     __device__ static R load(const T* p) { return float(*p); }
     __device__ static void store(T* p, R v) { *p = __bf16(v); }
 };

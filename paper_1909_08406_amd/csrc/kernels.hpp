@@ -598,6 +598,23 @@ __device__ __forceinline__ void wall_pull(typename ST::R x[Q], const char* __res
     });
 }
 
+// Stochastic rounding to FP16 saturates at the largest finite magnitude
+// instead of overflowing (see StoreF16S::encode_sr2): a stored value of that
+// magnitude is flagged when it is read back. One max of three magnitudes
+// per pair of the decoded inputs (written out: the library's fmaxf would
+// first quiet possible signalling NaNs of every input).
+template <class ST, bool SR>
+__device__ __forceinline__ void flag_saturated(const typename ST::R x[Q], const StepParams& p)
+{
+    if constexpr (SR && ST::SAT > 0.f) {
+        float amax = 0.f;
+#pragma unroll
+        for (int k = 0; k + 1 < Q; k += 2) asm("v_max3_f32 %0, |%1|, |%2|, %0" : "+v"(amax) : "v"(x[k]), "v"(x[k + 1]));
+        asm("v_max3_f32 %0, |%1|, |%1|, %0" : "+v"(amax) : "v"(x[Q - 1]));
+        if (__builtin_expect(!(amax < ST::SAT), 0)) atomicOr(p.flag, 1u);
+    }
+}
+
 // The step of node n of one box: src and dst are the box's first q-block
 // in the current and the other population buffer.
 template <class ST, int NEWTON, int FL, bool SR, int MODEL>
@@ -633,6 +650,7 @@ __device__ __forceinline__ void step_node(const char* __restrict__ src, char* __
             if constexpr (q % 2 == 0) pk[q / 2] = b;
             else pk[q / 2] |= b << 16;
         });
+        flag_saturated<ST, SR>(x, p);
         // keep the packed words opaque, so the relaxation cannot reuse x
 #pragma unroll
         for (int k = 0; k < QP; ++k) asm volatile("" : "+v"(pk[k]));
@@ -647,6 +665,7 @@ __device__ __forceinline__ void step_node(const char* __restrict__ src, char* __
             x[q] = ST::decode(ld_hint(reinterpret_cast<const T*>(src + q * qbytes + uint64_t(pull_src<q>(nb))),
                                       FL & FL_NT_LOAD));
         });
+        flag_saturated<ST, SR>(x, p);
         if constexpr ((MODEL & MODEL_WALLS) != 0) {
             // the pulls above wrapped periodically (in bounds); the ones
             // from beyond a wall are replaced
@@ -671,6 +690,34 @@ __global__ __launch_bounds__(BLK) void k_step(const typename ST::T* __restrict__
     const uint32_t n = blk * BLK + threadIdx.x;
     if (n >= p.g.N) return;
     step_node<ST, NEWTON, FL, SR, MODEL>(reinterpret_cast<const char*>(fin), reinterpret_cast<char*>(fout), p, n);
+}
+
+// Collisionless streaming (free flight): every population moves along its
+// link unchanged, the update of Sec. II without the collision term. The
+// same pull addressing, loads and stores as k_step (T: the stored type), a
+// pure permutation of the stored values.
+template <class T, int BLK, int FL>
+__global__ __launch_bounds__(BLK) void k_stream_free(const T* __restrict__ fin, T* __restrict__ fout, StepParams p)
+{
+    const uint32_t blk = p.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t n = blk * BLK + threadIdx.x;
+    if (n >= p.g.N) return;
+    const Coord c = decode(n, p.g);
+    Nbr nb;
+    make_nbr(p.g, c, nb, uint32_t(sizeof(T)));
+    const uint64_t qbytes = uint64_t(p.g.qs) * sizeof(T);
+    const char* src = reinterpret_cast<const char*>(fin);
+    char* dst = reinterpret_cast<char*>(fout);
+    T v[Q];
+    static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        v[q] = ld_hint(reinterpret_cast<const T*>(src + q * qbytes + uint64_t(pull_src<q>(nb))), FL & FL_NT_LOAD);
+    });
+    const uint32_t nbytes = n * uint32_t(sizeof(T));
+    static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        st_hint(reinterpret_cast<T*>(dst + q * qbytes + uint64_t(nbytes)), v[q], FL & FL_NT_STORE);
+    });
 }
 
 // ---------------------------------------------------------------------------

@@ -205,14 +205,23 @@ constexpr int TOTAL_BLOCKS = 1024;
 
 // Per-block partial sums of the node moments (fixed assignment of nodes to
 // threads, so the result does not depend on timing).
+// sat_check: flag a stored magnitude at the saturation value of the
+// stochastic-rounding FP16 encoder (contexts with stochastic rounding).
 template <class ST>
 __global__ __launch_bounds__(BLOCK) void k_totals(const typename ST::T* __restrict__ f, uint32_t N, StepParams p,
-                                                  double* __restrict__ partials)
+                                                  double* __restrict__ partials, uint32_t sat_check = 0)
 {
     double acc[5] = {0, 0, 0, 0, 0};
     for (uint32_t n = blockIdx.x * BLOCK + threadIdx.x; n < N; n += gridDim.x * BLOCK) {
         double m[5];
         node_moments64<ST>(f, p.g.qs, n, p, m);
+        if constexpr (ST::SAT > 0.f) {
+            if (sat_check) {
+                bool sat = false;
+                for (int q = 0; q < Q; ++q) sat |= !(fabsf(float(f[size_t(q) * p.g.qs + n])) < ST::SAT);
+                if (sat) atomicOr(p.flag, 1u);
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 5; ++k) acc[k] += m[k];
     }

@@ -12,7 +12,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -406,6 +409,333 @@ void set_shift(lbm_ctx* ctx)
 }  // namespace
 
 namespace {
+
+// ---------------------------------------------------------------------------
+// Autotuner: times launch configurations of the step on the context's own
+// boxes without changing the held state, and keeps the fastest.
+// ---------------------------------------------------------------------------
+
+// Tuning choices already made in this process (and optionally a file),
+// keyed by what the step's speed depends on: the device architecture, the
+// storage form, the kernel model, the rounding, the Newton count and the
+// box shapes. Thread-safe.
+class TuneCache {
+public:
+    bool find(const std::string& key, lbm_tuning* t)
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        auto it = map_.find(key);
+        if (it == map_.end()) return false;
+        *t = it->second;
+        return true;
+    }
+    void insert(const std::string& key, const lbm_tuning& t)
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        map_[key] = t;
+        if (!file_.empty()) {
+            if (FILE* f = std::fopen(file_.c_str(), "a")) {
+                std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), t.variant, t.xcd_remap, t.schedule, t.graph_steps);
+                std::fclose(f);
+            }
+        }
+    }
+    // Entries of the file are loaded (malformed lines are skipped); new
+    // entries are appended to it. NULL: in-process only.
+    int set_file(const char* path)
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        if (!path) {
+            file_.clear();
+            return LBM_OK;
+        }
+        FILE* f = std::fopen(path, "a+");
+        if (!f) return LBM_E_ARG;
+        std::rewind(f);
+        char key[4096];
+        lbm_tuning t;
+        for (;;) {
+            const int n = std::fscanf(f, "%4095s %d %d %d %d", key, &t.variant, &t.xcd_remap, &t.schedule,
+                                      &t.graph_steps);
+            if (n == EOF) break;
+            if (n != 5) {
+                int c;
+                while ((c = std::fgetc(f)) != EOF && c != '\n') {
+                }
+                continue;
+            }
+            if (tuning_valid(t)) map_[key] = t;
+        }
+        std::fclose(f);
+        file_ = path;
+        return LBM_OK;
+    }
+    void clear()
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        map_.clear();
+    }
+    int count()
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        return int(map_.size());
+    }
+    static bool tuning_valid(const lbm_tuning& t)
+    {
+        return t.variant >= 0 && t.variant < NVARIANTS && (t.xcd_remap == 0 || t.xcd_remap == 1) &&
+               (t.schedule == LBM_SCHEDULE_PER_BOX || t.schedule == LBM_SCHEDULE_BATCHED) && t.graph_steps >= 0 &&
+               t.graph_steps <= LBM_GRAPH_STEPS_MAX && t.graph_steps % 2 == 0;
+    }
+
+private:
+    std::mutex mu_;
+    std::map<std::string, lbm_tuning> map_;
+    std::string file_;
+};
+
+TuneCache& tune_cache()
+{
+    static TuneCache c;
+    return c;
+}
+
+// Cache key of a context: architecture, storage, model, rounding, Newton
+// steps and the box shapes (listed for up to four boxes, else their count
+// and a 64-bit FNV-1a hash of the shapes). No spaces.
+int tune_key(lbm_ctx* ctx, uint32_t flags, std::string* key)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    char arch[64];
+    std::snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+    for (char* c = arch; *c; ++c)
+        if (*c == ' ' || *c == ':') *c = '_';
+    char head[256];
+    std::snprintf(head, sizeof(head), "%s|st%d|m%u|sr%d|nw%d|f%u|nb%zu", arch, ctx->storage, ctx->base.model,
+                  ctx->stochastic ? 1 : 0, ctx->newton, flags & (LBM_TUNE_SCHEDULE | LBM_TUNE_GRAPH),
+                  ctx->boxes.size());
+    std::string k = head;
+    if (ctx->boxes.size() <= 4) {
+        for (const BoxDev& b : ctx->boxes) {
+            char d[64];
+            std::snprintf(d, sizeof(d), "|%ux%ux%u", b.g.nx, b.g.ny, b.g.nz);
+            k += d;
+        }
+    } else {
+        uint64_t h = 1469598103934665603ull;
+        for (const BoxDev& b : ctx->boxes) {
+            for (uint32_t v : {b.g.nx, b.g.ny, b.g.nz}) {
+                for (int i = 0; i < 4; ++i) {
+                    h ^= (v >> (8 * i)) & 0xffu;
+                    h *= 1099511628211ull;
+                }
+            }
+        }
+        char d[32];
+        std::snprintf(d, sizeof(d), "|h%016llx", static_cast<unsigned long long>(h));
+        k += d;
+    }
+    *key = k;
+    return LBM_OK;
+}
+
+// Mean time per step of one launch configuration: `reps` steps (after one
+// untimed step), or for graph_steps G > 0 whole replays of a captured
+// graph of G steps (at least `reps` steps). Every timed launch reads the
+// current buffer and writes the other one: the held state is unchanged.
+int time_config(lbm_ctx* ctx, const lbm_tuning& t, int32_t reps, hipEvent_t e0, hipEvent_t e1, float* ms)
+{
+    const int sv = ctx->variant, ss = ctx->schedule;
+    const uint32_t sx = ctx->base.xcd_remap;
+    ctx->variant = t.variant;
+    ctx->base.xcd_remap = uint32_t(t.xcd_remap);
+    ctx->schedule = t.schedule;
+    int rc = LBM_OK;
+    float el = 0.f;
+    int steps = 0;
+    if (t.graph_steps == 0) {
+        for (int r = -1; r < reps && rc == LBM_OK; ++r) {
+            if (r == 0 && hipEventRecord(e0, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
+            if (rc == LBM_OK) rc = enqueue_step(ctx, ctx->cur, ctx->steps_done, nullptr, ctx->stream);
+        }
+        steps = reps;
+    } else {
+        if (!ctx->capture && hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking) != hipSuccess)
+            rc = LBM_E_HIP;
+        hipGraphExec_t exec = nullptr;
+        if (rc == LBM_OK && hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            rc = LBM_E_HIP;
+        if (rc == LBM_OK) {
+            int crc = LBM_OK;
+            for (int i = 0; i < t.graph_steps && crc == LBM_OK; ++i)
+                crc = enqueue_step(ctx, ctx->cur, uint32_t(i), ctx->step_ctr, ctx->capture);
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(ctx->capture, &graph);
+            if (crc == LBM_OK && e == hipSuccess && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                crc = LBM_E_HIP;
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) crc = LBM_E_HIP;
+            rc = crc;
+            (void)hipGetLastError();
+        }
+        const int replays = std::max(1, (reps + t.graph_steps - 1) / t.graph_steps);
+        for (int r = -1; r < replays && rc == LBM_OK; ++r) {
+            if (r == 0 && hipEventRecord(e0, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
+            if (rc == LBM_OK && hipGraphLaunch(exec, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
+        }
+        steps = replays * t.graph_steps;
+        if (rc == LBM_OK && hipEventRecord(e1, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
+        if (rc == LBM_OK && hipEventSynchronize(e1) != hipSuccess) rc = LBM_E_HIP;
+        if (rc == LBM_OK && hipEventElapsedTime(&el, e0, e1) != hipSuccess) rc = LBM_E_HIP;
+        if (exec) {
+            (void)hipStreamSynchronize(ctx->stream);
+            (void)hipGraphExecDestroy(exec);
+        }
+        ctx->variant = sv;
+        ctx->base.xcd_remap = sx;
+        ctx->schedule = ss;
+        if (rc == LBM_OK) *ms = el / float(steps);
+        return rc;
+    }
+    if (rc == LBM_OK && hipEventRecord(e1, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
+    if (rc == LBM_OK && hipEventSynchronize(e1) != hipSuccess) rc = LBM_E_HIP;
+    if (rc == LBM_OK && hipEventElapsedTime(&el, e0, e1) != hipSuccess) rc = LBM_E_HIP;
+    ctx->variant = sv;
+    ctx->base.xcd_remap = sx;
+    ctx->schedule = ss;
+    if (rc == LBM_OK) *ms = el / float(steps);
+    return rc;
+}
+
+// Timing noise below which configurations count as tied (relative).
+constexpr float TUNE_TIE = 0.005f;
+// graph_steps candidates besides eager launches.
+constexpr int TUNE_GRAPH_STEPS[] = {16, 64};
+
+// The search: every (variant, XCD remap) pair with the context's schedule,
+// eager, in three interleaved rounds (each configuration keeps its fastest
+// round); then, on request, the schedule and graph_steps with the chosen
+// pair. Among configurations within TUNE_TIE of the fastest, the one with
+// the XCD remap on is preferred (it moves no more than the algorithmic HBM
+// bytes), then eager launches. The choice is applied to the context.
+int autotune_impl(lbm_ctx* ctx, int32_t reps, uint32_t flags, float* ms, lbm_tune_result* res)
+{
+    if (!ctx || reps < 1) return LBM_E_ARG;
+    std::string key;
+    if (flags & LBM_TUNE_CACHE) {
+        int rc = tune_key(ctx, flags, &key);
+        if (rc) return rc;
+        lbm_tuning t;
+        if (tune_cache().find(key, &t)) {
+            rc = lbm_set_tuning(ctx, &t);
+            if (rc) return rc;
+            res->best = t;
+            res->best_ms = 0.f;
+            res->from_cache = 1;
+            res->timed = 0;
+            if (ms)
+                for (int k = 0; k < 2 * NVARIANTS; ++k) ms[k] = 0.f;
+            return LBM_OK;
+        }
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return LBM_E_HIP;
+    }
+    // captured graphs of the old configuration are dropped when the choice
+    // differs (lbm_set_tuning below); the stream is idle after timing
+    int rc = LBM_OK;
+    int timed = 0;
+    constexpr int ROUNDS = 3;
+    // variant x remap (the models other than E2 run one launch shape, so
+    // only the remap is timed for them)
+    const int nvar = ctx->base.model == MODEL_E2 ? NVARIANTS : 1;
+    float tmin[2 * NVARIANTS];
+    for (int k = 0; k < 2 * NVARIANTS; ++k) tmin[k] = 0.f;
+    for (int round = 0; round < ROUNDS && rc == LBM_OK; ++round)
+        for (int v = 0; v < nvar && rc == LBM_OK; ++v)
+            for (int x = 0; x < 2 && rc == LBM_OK; ++x) {
+                float t = 0.f;
+                rc = time_config(ctx, lbm_tuning{v, x, ctx->schedule, 0}, reps, e0, e1, &t);
+                if (rc == LBM_OK && (tmin[2 * v + x] == 0.f || t < tmin[2 * v + x])) tmin[2 * v + x] = t;
+                ++timed;
+            }
+    lbm_tuning bt{ctx->variant, int32_t(ctx->base.xcd_remap), ctx->schedule, 0};
+    float best_ms = 0.f;
+    if (rc == LBM_OK) {
+        for (int k = 0; k < 2 * nvar; ++k)
+            if (best_ms == 0.f || tmin[k] < best_ms) best_ms = tmin[k];
+        // ties (within noise) go to the remap, then to the lower index
+        int pick = -1;
+        for (int pass = 0; pass < 2 && pick < 0; ++pass)
+            for (int k = 0; k < 2 * nvar && pick < 0; ++k)
+                if ((pass == 1 || k % 2 == 1) && tmin[k] <= best_ms * (1.f + TUNE_TIE)) pick = k;
+        bt.variant = pick / 2;
+        bt.xcd_remap = pick % 2;
+        best_ms = tmin[pick];
+        if (ms)
+            for (int k = 0; k < 2 * NVARIANTS; ++k) ms[k] = k < 2 * nvar ? tmin[k] : 0.f;
+    }
+    // schedule (only meaningful with several boxes)
+    if (rc == LBM_OK && (flags & LBM_TUNE_SCHEDULE) && ctx->boxes.size() > 1) {
+        float ts[2] = {0.f, 0.f};
+        for (int round = 0; round < ROUNDS && rc == LBM_OK; ++round)
+            for (int sc = 0; sc < 2 && rc == LBM_OK; ++sc) {
+                float t = 0.f;
+                rc = time_config(ctx, lbm_tuning{bt.variant, bt.xcd_remap, sc, 0}, reps, e0, e1, &t);
+                if (rc == LBM_OK && (ts[sc] == 0.f || t < ts[sc])) ts[sc] = t;
+                ++timed;
+            }
+        if (rc == LBM_OK) {
+            // the current schedule unless the other is faster beyond noise
+            const int other = 1 - bt.schedule;
+            if (ts[other] < ts[bt.schedule] * (1.f - TUNE_TIE)) bt.schedule = other;
+            best_ms = ts[bt.schedule];
+        }
+    }
+    // graph replays of G steps against eager launches
+    if (rc == LBM_OK && (flags & LBM_TUNE_GRAPH)) {
+        constexpr int NG = int(sizeof(TUNE_GRAPH_STEPS) / sizeof(TUNE_GRAPH_STEPS[0]));
+        float tg[NG + 1];
+        for (int k = 0; k <= NG; ++k) tg[k] = 0.f;
+        for (int round = 0; round < ROUNDS && rc == LBM_OK; ++round)
+            for (int k = 0; k <= NG && rc == LBM_OK; ++k) {
+                const int g = k == 0 ? 0 : TUNE_GRAPH_STEPS[k - 1];
+                float t = 0.f;
+                rc = time_config(ctx, lbm_tuning{bt.variant, bt.xcd_remap, bt.schedule, g}, reps, e0, e1, &t);
+                if (rc == LBM_OK && (tg[k] == 0.f || t < tg[k])) tg[k] = t;
+                ++timed;
+            }
+        if (rc == LBM_OK) {
+            int pick = 0;
+            for (int k = 1; k <= NG; ++k)
+                if (tg[k] < tg[pick] * (1.f - TUNE_TIE)) pick = k;
+            bt.graph_steps = pick == 0 ? 0 : TUNE_GRAPH_STEPS[pick - 1];
+            best_ms = tg[pick];
+        }
+    } else {
+        bt.graph_steps = ctx->graph_steps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != LBM_OK) return rc;
+    rc = lbm_set_tuning(ctx, &bt);
+    if (rc) return rc;
+    if (flags & LBM_TUNE_CACHE) tune_cache().insert(key, bt);
+    res->best = bt;
+    res->best_ms = best_ms;
+    res->from_cache = 0;
+    res->timed = timed;
+    return LBM_OK;
+}
+
+}  // namespace
+
+namespace {
 template <typename R, int NEWTON>
 void collide_host(double omega, int model, const double* in, double* out)
 {
@@ -634,6 +964,54 @@ int lbm_step(lbm_ctx* ctx, int32_t n)
     return LBM_OK;
 }
 
+int lbm_stream_free(lbm_ctx* ctx, int32_t n)
+{
+    if (!ctx || n < 0) return LBM_E_ARG;
+    if (ctx->base.model & MODEL_WALLS) return LBM_E_UNSUPPORTED;
+#if defined(LBM_HOST_CHECK)
+    return n == 0 ? LBM_OK : LBM_E_UNSUPPORTED;
+#else
+    // the launch shape of the energy-conserving step: the context's variant
+    // and tile mapping (other models run 256 threads without hints)
+    const int v = ctx->base.model == MODEL_E2 ? ctx->variant : 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int eb = elem_bytes(ctx->storage);
+        int rc = LBM_OK;
+        auto launch = [&](auto tag, auto blk, auto fl) {
+            using T = decltype(tag);
+            constexpr int BLK = decltype(blk)::value;
+            constexpr int FL = decltype(fl)::value;
+            const T* in = reinterpret_cast<const T*>(ctx->buf(ctx->cur));
+            T* out = reinterpret_cast<T*>(ctx->buf(1 - ctx->cur));
+            for (const BoxDev& b : ctx->boxes) {
+                const StepParams p = ctx->params(b);
+                hipLaunchKernelGGL((k_stream_free<T, BLK, FL>), dim3(uint32_t((b.nodes + BLK - 1) / BLK)), dim3(BLK), 0,
+                                   ctx->stream, in + b.offset, out + b.offset, p);
+            }
+        };
+        auto by_type = [&](auto blk, auto fl) {
+            if (eb == 8) launch(double{}, blk, fl);
+            else if (eb == 4) launch(float{}, blk, fl);
+            else launch(uint16_t{}, blk, fl);
+        };
+        using std::integral_constant;
+        switch (v) {
+            case 0: by_type(integral_constant<int, 256>{}, integral_constant<int, 0>{}); break;
+            case 1: by_type(integral_constant<int, 256>{}, integral_constant<int, FL_NT_LOAD | FL_NT_STORE>{}); break;
+            case 2: by_type(integral_constant<int, 512>{}, integral_constant<int, 0>{}); break;
+            case 3: by_type(integral_constant<int, 128>{}, integral_constant<int, 0>{}); break;
+            case 4: by_type(integral_constant<int, 256>{}, integral_constant<int, FL_NT_STORE>{}); break;
+            case 5: by_type(integral_constant<int, 1024>{}, integral_constant<int, 0>{}); break;
+            default: rc = LBM_E_ARG; break;
+        }
+        if (rc) return rc;
+        HIPCHK(hipGetLastError());
+        ctx->cur ^= 1;
+    }
+    return LBM_OK;
+#endif
+}
+
 int lbm_synchronize(lbm_ctx* ctx)
 {
     if (!ctx) return LBM_E_ARG;
@@ -693,7 +1071,7 @@ int lbm_totals(lbm_ctx* ctx, double* out)
             using T = typename ST::T;
             const T* f = reinterpret_cast<const T*>(ctx->buf(ctx->cur)) + b.offset;
             hipLaunchKernelGGL((k_totals<ST>), dim3(nblk), dim3(BLOCK), 0, ctx->stream, f, uint32_t(b.nodes), p,
-                               ctx->partials);
+                               ctx->partials, uint32_t(ctx->stochastic));
             hipLaunchKernelGGL(k_reduce_partials<5>, dim3(1), dim3(BLOCK), 0, ctx->stream, ctx->partials, nblk, res);
             return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
         });
@@ -911,67 +1289,30 @@ int lbm_get_tuning(lbm_ctx* ctx, lbm_tuning* t)
 
 int lbm_autotune(lbm_ctx* ctx, int32_t reps, float* ms, lbm_tuning* best)
 {
-    if (!ctx || reps < 1) return LBM_E_ARG;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return LBM_E_HIP;
-    }
-    const int saved_v = ctx->variant;
-    const uint32_t saved_x = ctx->base.xcd_remap;
-    int rc = LBM_OK;
-    lbm_tuning bt{saved_v, int32_t(saved_x), ctx->schedule, ctx->graph_steps};
-    // every configuration is timed once per round, the rounds interleaved,
-    // and keeps its fastest round (less bias from clock ramps and drift than
-    // timing each configuration once in a fixed order)
-    constexpr int ROUNDS = 3;
-    float tmin[2 * NVARIANTS];
-    for (int k = 0; k < 2 * NVARIANTS; ++k) tmin[k] = 0.f;
-    for (int round = 0; round < ROUNDS && rc == LBM_OK; ++round) {
-        for (int v = 0; v < NVARIANTS && rc == LBM_OK; ++v) {
-            for (int x = 0; x < 2 && rc == LBM_OK; ++x) {
-                ctx->variant = v;
-                ctx->base.xcd_remap = uint32_t(x);
-                // reads the current buffer, writes the other one, never flips:
-                // the held state is left unchanged
-                for (int r = -1; r < reps && rc == LBM_OK; ++r) {
-                    if (r == 0 && hipEventRecord(e0, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
-                    if (rc == LBM_OK) rc = enqueue_step(ctx, ctx->cur, ctx->steps_done, nullptr, ctx->stream);
-                }
-                if (rc == LBM_OK && hipEventRecord(e1, ctx->stream) != hipSuccess) rc = LBM_E_HIP;
-                if (rc == LBM_OK && hipEventSynchronize(e1) != hipSuccess) rc = LBM_E_HIP;
-                float t = 0.f;
-                if (rc == LBM_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = LBM_E_HIP;
-                t /= float(reps);
-                if (rc == LBM_OK && (tmin[2 * v + x] == 0.f || t < tmin[2 * v + x])) tmin[2 * v + x] = t;
-            }
-        }
-    }
-    float best_ms = 0.f;
-    for (int v = 0; v < NVARIANTS && rc == LBM_OK; ++v)
-        for (int x = 0; x < 2; ++x) {
-            const float t = tmin[2 * v + x];
-            if (ms) ms[2 * v + x] = t;
-            if (best_ms == 0.f || t < best_ms) {
-                best_ms = t;
-                bt.variant = v;
-                bt.xcd_remap = x;
-            }
-        }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (rc != LBM_OK) {
-        ctx->variant = saved_v;
-        ctx->base.xcd_remap = saved_x;
-        return rc;
-    }
-    if (bt.variant != saved_v || uint32_t(bt.xcd_remap) != saved_x) drop_graphs(ctx);  // stream is idle here
-    ctx->variant = bt.variant;
-    ctx->base.xcd_remap = uint32_t(bt.xcd_remap);
-    if (best) *best = bt;
+    lbm_tune_result r{};
+    const int rc = autotune_impl(ctx, reps, 0u, ms, &r);
+    if (rc == LBM_OK && best) *best = r.best;
+    return rc;
+}
+
+int lbm_autotune_ex(lbm_ctx* ctx, int32_t reps, uint32_t flags, float* ms, lbm_tune_result* res)
+{
+    if (flags & ~uint32_t(LBM_TUNE_SCHEDULE | LBM_TUNE_GRAPH | LBM_TUNE_CACHE)) return LBM_E_ARG;
+    lbm_tune_result r{};
+    const int rc = autotune_impl(ctx, reps, flags, ms, &r);
+    if (rc == LBM_OK && res) *res = r;
+    return rc;
+}
+
+int lbm_tune_cache_file(const char* path) { return tune_cache().set_file(path); }
+
+int lbm_tune_cache_clear(void)
+{
+    tune_cache().clear();
     return LBM_OK;
 }
+
+int lbm_tune_cache_count(void) { return tune_cache().count(); }
 
 void* lbm_stream(lbm_ctx* ctx) { return ctx ? reinterpret_cast<void*>(ctx->stream) : nullptr; }
 

@@ -58,7 +58,13 @@ class Tuning(ctypes.Structure):
 
 
 # lbm_schedule: one launch per box, or one launch over every (box, tile)
+class TuneResult(ctypes.Structure):
+    _fields_ = [("best", Tuning), ("best_ms", ctypes.c_float), ("from_cache", ctypes.c_int32),
+                ("timed", ctypes.c_int32)]
+
+
 SCHEDULES = {"per_box": 0, "batched": 1}
+TUNE_SCHEDULE, TUNE_GRAPH, TUNE_CACHE = 1, 2, 4
 GRAPH_STEPS_MAX = 1024
 
 
@@ -95,6 +101,12 @@ SIGNATURES = {
     "lbm_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "lbm_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "lbm_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(Tuning)]),
+    "lbm_autotune_ex": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_float),
+                                       ctypes.POINTER(TuneResult)]),
+    "lbm_stream_free": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "lbm_tune_cache_file": (ctypes.c_int, [ctypes.c_char_p]),
+    "lbm_tune_cache_clear": (ctypes.c_int, []),
+    "lbm_tune_cache_count": (ctypes.c_int, []),
     "lbm_stream": (_vp, [_vp]),
     "lbm_free": (None, [_vp]),
     "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -185,6 +197,10 @@ class Context:
 
     def step(self, n=1):
         _check(lib().lbm_step(self.handle, int(n)), "lbm_step")
+
+    def stream_free(self, n=1):
+        """n collisionless streaming steps (an exact permutation of the held values)."""
+        _check(lib().lbm_stream_free(self.handle, int(n)), "lbm_stream_free")
 
     def synchronize(self):
         _check(lib().lbm_synchronize(self.handle), "lbm_synchronize")
@@ -298,6 +314,17 @@ class Context:
         _check(lib().lbm_autotune(self.handle, int(reps), ms, ctypes.byref(best)), "lbm_autotune")
         return (best.variant, best.xcd_remap), {(v, x): ms[2 * v + x] for v in range(nv) for x in range(2)}
 
+    def autotune_ex(self, reps=3, schedule=True, graph=True, cache=True):
+        """The wider search with the tuning cache (lbm_autotune_ex): returns
+        a dict with the chosen settings, best_ms, from_cache and timed."""
+        flags = (TUNE_SCHEDULE if schedule else 0) | (TUNE_GRAPH if graph else 0) | (TUNE_CACHE if cache else 0)
+        r = TuneResult()
+        _check(lib().lbm_autotune_ex(self.handle, int(reps), flags, None, ctypes.byref(r)), "lbm_autotune_ex")
+        names = {v: k for k, v in SCHEDULES.items()}
+        return {"variant": r.best.variant, "xcd_remap": r.best.xcd_remap,
+                "schedule": names.get(r.best.schedule, r.best.schedule), "graph_steps": r.best.graph_steps,
+                "best_ms": r.best_ms, "from_cache": bool(r.from_cache), "timed": r.timed}
+
     def free(self):
         if self._h is not None:
             lib().lbm_free(self._h)
@@ -389,6 +416,19 @@ def collide_host(f, omega, precision="f32", newton=None, isothermal=False, serie
     _check(lib().lbm_collide_host(pr, nt, flags, float(omega), _d(f), _d(out)),
            "lbm_collide_host")
     return out
+
+
+def tune_cache_file(path):
+    """Back the process-wide tuning cache with a text file (None: in-process only)."""
+    _check(lib().lbm_tune_cache_file(None if path is None else str(path).encode()), "lbm_tune_cache_file")
+
+
+def tune_cache_clear():
+    _check(lib().lbm_tune_cache_clear(), "lbm_tune_cache_clear")
+
+
+def tune_cache_count():
+    return int(lib().lbm_tune_cache_count())
 
 
 def num_variants():

@@ -186,6 +186,73 @@ def test_taylor_green_256_conservation(L, ma, tau, storage, sr):
     assert nodes > 0
 
 
+def solenoidal_kinetic_energy(m, n):
+    """Kinetic energy of the divergence-free part of the flow of an n^3 box
+    from its node moments: on each sublattice (a periodic n^3 grid) the
+    field w = j / sqrt(rho), whose |w|^2 / 2 is the kinetic energy density,
+    is projected onto divergence-free Fourier modes and its energy summed by
+    Parseval (real FFT: the interior of the last axis counts twice)."""
+    kz = np.fft.fftfreq(n)[:, None, None]
+    ky = np.fft.fftfreq(n)[None, :, None]
+    kx = np.fft.rfftfreq(n)[None, None, :]
+    k2 = kx ** 2 + ky ** 2 + kz ** 2
+    k2[0, 0, 0] = 1.0
+    weight = np.full(kx.shape, 2.0)
+    weight[..., 0] = 1.0
+    if n % 2 == 0:
+        weight[..., -1] = 1.0
+    total = 0.0
+    n3 = n ** 3
+    for s in (0, 1):
+        sl = slice(s * n3, (s + 1) * n3)
+        r = np.sqrt(m[0, sl])
+        W = [np.fft.rfftn((m[1 + a, sl] / r).reshape(n, n, n)) for a in range(3)]  # x, y, z components
+        kdw = kx * W[0] + ky * W[1] + kz * W[2]
+        for a, ka in enumerate((kx, ky, kz)):
+            P = W[a] - ka * kdw / k2
+            total += 0.5 * float(np.sum(weight * (P.real ** 2 + P.imag ** 2))) / n3
+    return total
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_taylor_green_256_early_laminar_decay(L, storage):
+    """Plain method, 256^3 Taylor-Green vortex at Ma 0.1 (tau 0.50605,
+    Re 1600): before the vortex stretching has built up enstrophy, the
+    kinetic energy decays at the laminar rate of the initial mode. The
+    velocity field is an eigenfunction of the Laplacian with eigenvalue
+    -3/L^2 (L = n / 2 pi), so dKE/dt = -2 nu Omega gives 6 nu / L^2.
+
+    The initial field carries no pressure correction, so acoustic waves
+    trade kinetic with compression energy at the rate the viscous decay
+    has (a fit of the whole kinetic energy over 100 steps gives 6 times the
+    laminar rate). Those waves are curl-free: the energy of the
+    divergence-free part of the flow is free of them and decays by
+    viscosity, at the laminar rate until stretching changes the enstrophy
+    at second order in t / t_c (t_c = L / U0 = 580 steps)."""
+    n, tau, ma = 256, 0.50605, 0.1
+    _, _, th = L.lattice()
+    u0 = ma * np.sqrt(5.0 / 3.0 * th)
+    F = wl.taylor_green(n, u0)
+    ctx = L.init([(n, n, n, tau)], *F.absolute(th), storage=storage)
+    ts, ke = [], []
+    for t in range(0, 101, 20):
+        if t:
+            ctx.step(20)
+        m = ctx.moments()
+        ke.append(solenoidal_kinetic_energy(m, n))
+        ts.append(t)
+        del m
+    ctx.free()
+    ts, ke = np.array(ts, dtype=float), np.array(ke)
+    nu = th * (tau - 0.5)
+    rate = 6.0 * nu / (n / (2 * np.pi)) ** 2
+    fit = -np.polyfit(ts, np.log(ke), 1)[0]
+    say("C3 early decay %s: laminar 6 nu/L^2 = %.4e per step; divergence-free kinetic energy over 100 steps "
+        "decays at %.4e (ratio %.4f); KE_sol/KE_sol(0) = %s" % (storage, rate, fit, fit / rate,
+                                                                 ["%.6f" % v for v in ke / ke[0]]))
+    assert abs(fit / rate - 1) < 5e-2
+
+
 def _line_pressure(ctx, n, y0, z0, s=0):
     """p = rho theta along x at (y0, z0) on sublattice s, from gathered
     populations (x = 0..n-1)."""
@@ -201,8 +268,9 @@ def test_pulse_512_against_analytic_and_fp64(L, orc):
     amplitude 1e-3, half width 8 cells), 500 steps. The pressure p - rho0
     theta0 along the x axis through the centre follows theta0 times the
     analytic spherical wave with speed sqrt(gamma theta0) before the front
-    wraps; FP32 and the 16-bit shifted forms are compared with FP64 run on
-    the GPU (itself checked against the oracle at smaller sizes)."""
+    wraps; FP32 and the 16-bit shifted forms, with round to nearest and
+    with stochastic rounding (the benchmarked form), are compared with FP64
+    run on the GPU (itself checked against the oracle at smaller sizes)."""
     n, tau, eps, b = 512, 0.6, 1e-3, 8.0
     _, _, th = L.lattice()
     c, w, _ = orc.lattice()
@@ -212,8 +280,10 @@ def test_pulse_512_against_analytic_and_fp64(L, orc):
     nu = an.viscosity(th, tau)
     xs = np.arange(n) - n / 2
     lines = {}
-    for storage in ("f64", "f32", "f16s", "bf16s"):
-        ctx = L.init([(n, n, n, tau)], *F.absolute(th), storage=storage)
+    for storage, sr in (("f64", False), ("f32", False), ("f16s", False), ("bf16s", False), ("f16s", True),
+                        ("bf16s", True)):
+        form = storage + ("+sr" if sr else "")
+        ctx = L.init([(n, n, n, tau)], *F.absolute(th), storage=storage, stochastic=sr)
         tot0 = ctx.totals()[0]
         got = {}
         done = 0
@@ -228,15 +298,17 @@ def test_pulse_512_against_analytic_and_fp64(L, orc):
             got[t] = p - th
         tot1 = ctx.totals()[0]
         ctx.free()
-        lines[storage] = got
-        say("C4 %s: mass drift %.2e, energy drift %.2e" % (storage, tot1[0] / tot0[0] - 1, tot1[4] / tot0[4] - 1))
+        lines[form] = got
+        say("C4 %s: mass drift %.2e, energy drift %.2e" % (form, tot1[0] / tot0[0] - 1, tot1[4] / tot0[4] - 1))
     for t in (100, 200):
         ana = th * an.pulse_3d_integral(np.abs(xs), float(t), eps, b, cs, nu_eff=nu)
         err = np.max(np.abs(lines["f64"][t] - ana)) / (th * eps)
         say("C4 t=%d: FP64 vs analytic pulse, max error / (theta0 eps) = %.3e" % (t, err))
         assert err < 2e-2
-    for storage in ("f32", "f16s", "bf16s"):
+    # measured (round to nearest): FP32 <= 1.5e-4, FP16 <= 1.4e-4, BF16 <= 9.7e-4
+    # of theta0 eps; stochastic rounding is unbiased with the same quantum
+    for form in ("f32", "f16s", "bf16s", "f16s+sr", "bf16s+sr"):
         for t in (100, 200, 500):
-            e = np.max(np.abs(lines[storage][t] - lines["f64"][t])) / (th * eps)
-            say("C4 %s t=%d: error vs FP64 / (theta0 eps) = %.3e" % (storage, t, e))
-            assert e < {"f32": 1e-3, "f16s": 1e-2, "bf16s": 5e-2}[storage]
+            e = np.max(np.abs(lines[form][t] - lines["f64"][t])) / (th * eps)
+            say("C4 %s t=%d: error vs FP64 / (theta0 eps) = %.3e" % (form, t, e))
+            assert e < {"f32": 1e-3, "f16s": 2e-3, "bf16s": 1e-2}[form.split("+")[0]], (form, t, e)
