@@ -244,6 +244,30 @@ int lbm_moments(lbm_ctx *ctx, double *rho, double *jx, double *jy, double *jz, d
 int lbm_totals(lbm_ctx *ctx, double *out);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * conservation totals of lbm_totals for one box whose populations the
+ * caller holds in device memory, with no context and no allocation.
+ * f: device pointer to the box's first q-block, populations [q][node] in
+ * the storage form `storage` (lbm_storage), consecutive q-blocks `qstride`
+ * elements apart (qstride >= 2*nx*ny*nz; nodes ordered as in every host
+ * array); box: its dimensions (tau unused). Shifted forms hold
+ * (f - w_q rho0) 2^{k_q} with k_q = round(-log2 w_q) + shift_exp for
+ * LBM_F16_SHIFT and LBM_BF16_SHIFT (shift_exp as reported by lbm_get_info)
+ * and k_q = 0 for LBM_F32_SHIFT; rho0 = 0 means 1.0. out: device pointer to
+ * 5 doubles, (mass, Jx, Jy, Jz, E) summed in FP64 as lbm_totals does (the
+ * same result bit for bit). Queued on `stream` (a hipStream_t, NULL for the
+ * null stream) without synchronising.
+ * The per-block partial sums live in a fixed device array of the library
+ * (1024 x 5 doubles, one per device, kept until the process ends); calls
+ * that overlap on one device race on it. Largest input: fewer than 2^32
+ * nodes and a q-stride below 2^32 elements (else LBM_E_ARG).
+ * Errors: LBM_E_ARG, LBM_E_HIP, LBM_E_UNSUPPORTED (device index >= 64).
+ */
+int lbm_totals_noalloc(const void *f, int32_t storage, const lbm_box *box, uint64_t qstride, double rho0,
+                       int32_t shift_exp, void *stream, double *out);
+
+/*
  * Fourier amplitudes of the node fields of one box at wavevector k[3]
  * (radians per cell spacing): out[2f] + i out[2f+1] = (1/N) sum_n m_f(n)
  * exp(-i k.x_n) for m_f = rho, jx, jy, jz, E, theta (f = 0..5), with x_n the

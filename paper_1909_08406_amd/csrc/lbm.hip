@@ -735,6 +735,45 @@ int autotune_impl(lbm_ctx* ctx, int32_t reps, uint32_t flags, float* ms, lbm_tun
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of lbm_totals_noalloc: the per-block partial sums of its FP64
+// totals live in this fixed device array (one copy per device, held until
+// the process ends) instead of a context workspace.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr uint32_t NOALLOC_BLOCKS = TOTAL_BLOCKS;                 // partial-sum blocks
+constexpr size_t SCRATCH_DOUBLES = size_t(NOALLOC_BLOCKS) * 5;   // 40 KiB
+}  // namespace
+
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (with that device current) and kept: in host code the array's
+// name is not a device address.
+int scratch_on_current_device(double** out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return LBM_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return LBM_E_HIP;
+        }
+        g_scratch[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch[dev];
+    return LBM_OK;
+}
+}  // namespace
+
 namespace {
 template <typename R, int NEWTON>
 void collide_host(double omega, int model, const double* in, double* out)
@@ -1080,6 +1119,50 @@ int lbm_totals(lbm_ctx* ctx, double* out)
         HIPCHK(hipStreamSynchronize(ctx->stream));
     }
     return lbm_status(ctx);
+}
+
+int lbm_totals_noalloc(const void* f, int32_t storage, const lbm_box* box, uint64_t qstride, double rho0,
+                       int32_t shift_exp, void* stream, double* out)
+{
+    if (!f || !box || !out) return LBM_E_ARG;
+    const int eb = elem_bytes(storage);
+    if (eb == 0) return LBM_E_ARG;
+    if (box->nx < 1 || box->ny < 1 || box->nz < 1) return LBM_E_ARG;
+    const uint64_t nodes = 2ull * uint64_t(box->nx) * uint64_t(box->ny) * uint64_t(box->nz);
+    // the largest box: 32-bit node ids and q-block strides
+    if (nodes >= (1ull << 32) || qstride < nodes || qstride >= (1ull << 32)) return LBM_E_ARG;
+    const bool shifted = storage == LBM_F16_SHIFT || storage == LBM_BF16_SHIFT || storage == LBM_F32_SHIFT;
+    if (!(rho0 >= 0.0) || !std::isfinite(rho0)) return LBM_E_ARG;
+    if (rho0 == 0.0) rho0 = 1.0;
+    if ((storage == LBM_F16_SHIFT || storage == LBM_BF16_SHIFT) && (shift_exp < -60 || shift_exp > 60))
+        return LBM_E_ARG;
+    StepParams p{};
+    p.g = make_geom(uint32_t(box->nx), uint32_t(box->ny), uint32_t(box->nz));
+    p.g.qs = uint32_t(qstride);
+    for (int sh = 0; sh < 6; ++sh) {
+        const int k = storage == LBM_F32_SHIFT ? 0 : shift_exp + SHELL_K[sh];
+        p.scale[sh] = std::ldexp(1.0f, k);
+        p.inv_scale[sh] = std::ldexp(1.0f, -k);
+    }
+    double e2 = 0.0;  // sum_q w_q c_q^2 / 2 per unit reference density
+    for (int q = 0; q < Q; ++q)
+        e2 += SHELL_W[VEL[q].shell] * 0.25 * (VEL[q].x * VEL[q].x + VEL[q].y * VEL[q].y + VEL[q].z * VEL[q].z);
+    p.rho_ref = shifted ? rho0 : 0.0;
+    p.e2_ref = shifted ? e2 * rho0 : 0.0;
+    double* part = nullptr;
+    int rc = scratch_on_current_device(&part);
+    if (rc) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const uint32_t nblk = std::min<uint32_t>(NOALLOC_BLOCKS, nblocks(nodes));
+    return dispatch_storage(storage, [&](auto st) {
+        using ST = decltype(st);
+        using T = typename ST::T;
+        // every partial the reduction reads is written by k_totals first
+        hipLaunchKernelGGL((k_totals<ST>), dim3(nblk), dim3(BLOCK), 0, s, reinterpret_cast<const T*>(f),
+                           uint32_t(nodes), p, part, 0u);
+        hipLaunchKernelGGL(k_reduce_partials<5>, dim3(1), dim3(BLOCK), 0, s, part, nblk, out);
+        return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+    });
 }
 
 int lbm_project(lbm_ctx* ctx, int32_t box, const double* k, double* out)

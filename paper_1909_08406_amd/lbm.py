@@ -104,6 +104,8 @@ SIGNATURES = {
     "lbm_autotune_ex": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_float),
                                        ctypes.POINTER(TuneResult)]),
     "lbm_stream_free": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "lbm_totals_noalloc": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(Box), ctypes.c_uint64, ctypes.c_double,
+                                          ctypes.c_int32, _vp, _vp]),
     "lbm_tune_cache_file": (ctypes.c_int, [ctypes.c_char_p]),
     "lbm_tune_cache_clear": (ctypes.c_int, []),
     "lbm_tune_cache_count": (ctypes.c_int, []),
@@ -416,6 +418,19 @@ def collide_host(f, omega, precision="f32", newton=None, isothermal=False, serie
     _check(lib().lbm_collide_host(pr, nt, flags, float(omega), _d(f), _d(out)),
            "lbm_collide_host")
     return out
+
+
+def totals_noalloc(f_ptr, storage, dims, qstride, rho0=1.0, shift_exp=0, stream=None, out_ptr=None):
+    """lbm_totals_noalloc: FP64 totals of one box held in caller device
+    memory at f_ptr (populations [q][node], q-blocks qstride elements apart)
+    into 5 doubles at the device pointer out_ptr, queued on `stream` (a
+    torch.cuda.Stream, a raw handle or None)."""
+    box = Box(int(dims[0]), int(dims[1]), int(dims[2]), 0, 0.0)
+    h = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    _check(lib().lbm_totals_noalloc(ctypes.c_void_p(int(f_ptr)), STORAGE[storage] if isinstance(storage, str)
+                                    else int(storage), ctypes.byref(box), int(qstride), float(rho0), int(shift_exp),
+                                    ctypes.c_void_p(h) if h else None, ctypes.c_void_p(int(out_ptr))),
+           "lbm_totals_noalloc")
 
 
 def tune_cache_file(path):
