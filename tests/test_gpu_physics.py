@@ -186,71 +186,91 @@ def test_taylor_green_256_conservation(L, ma, tau, storage, sr):
     assert nodes > 0
 
 
-def solenoidal_kinetic_energy(m, n):
-    """Kinetic energy of the divergence-free part of the flow of an n^3 box
-    from its node moments: on each sublattice (a periodic n^3 grid) the
-    field w = j / sqrt(rho), whose |w|^2 / 2 is the kinetic energy density,
-    is projected onto divergence-free Fourier modes and its energy summed by
-    Parseval (real FFT: the interior of the last axis counts twice)."""
-    kz = np.fft.fftfreq(n)[:, None, None]
-    ky = np.fft.fftfreq(n)[None, :, None]
-    kx = np.fft.rfftfreq(n)[None, None, :]
+def solenoidal_energy_enstrophy(m, n):
+    """Kinetic energy and enstrophy of the divergence-free part of the flow
+    of an n^3 box from its node moments: on each sublattice (a periodic n^3
+    grid) the velocity u = j / rho is projected onto divergence-free Fourier
+    modes; KE = (rho_mean / 2) sum |P u|^2 and Omega = (rho_mean / 2) sum
+    |k|^2 |P u|^2 (= the vorticity's), summed by Parseval (real FFT: the
+    interior of the last axis counts twice). For such a field dKE/dt =
+    -2 nu Omega."""
+    kz = 2 * np.pi * np.fft.fftfreq(n)[:, None, None]
+    ky = 2 * np.pi * np.fft.fftfreq(n)[None, :, None]
+    kx = 2 * np.pi * np.fft.rfftfreq(n)[None, None, :]
     k2 = kx ** 2 + ky ** 2 + kz ** 2
-    k2[0, 0, 0] = 1.0
+    k2s = k2.copy()
+    k2s[0, 0, 0] = 1.0
     weight = np.full(kx.shape, 2.0)
     weight[..., 0] = 1.0
     if n % 2 == 0:
         weight[..., -1] = 1.0
-    total = 0.0
+    ke = om = 0.0
     n3 = n ** 3
+    rbar = float(m[0].mean())
     for s in (0, 1):
         sl = slice(s * n3, (s + 1) * n3)
-        r = np.sqrt(m[0, sl])
-        W = [np.fft.rfftn((m[1 + a, sl] / r).reshape(n, n, n)) for a in range(3)]  # x, y, z components
-        kdw = kx * W[0] + ky * W[1] + kz * W[2]
-        for a, ka in enumerate((kx, ky, kz)):
-            P = W[a] - ka * kdw / k2
-            total += 0.5 * float(np.sum(weight * (P.real ** 2 + P.imag ** 2))) / n3
-    return total
+        W = [np.fft.rfftn((m[1 + a, sl] / m[0, sl]).reshape(n, n, n)) for a in range(3)]  # x, y, z
+        kdw = (kx * W[0] + ky * W[1] + kz * W[2]) / k2s
+        e = sum(np.abs(W[a] - ka * kdw) ** 2 for a, ka in enumerate((kx, ky, kz)))
+        ke += 0.5 * rbar * float(np.sum(weight * e)) / n3
+        om += 0.5 * rbar * float(np.sum(weight * k2 * e)) / n3
+    return ke, om
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_taylor_green_256_early_laminar_decay(L, storage):
-    """Plain method, 256^3 Taylor-Green vortex at Ma 0.1 (tau 0.50605,
+def test_taylor_green_256_early_laminar_decay(L):
+    """Plain method, FP32, 256^3 Taylor-Green vortex at Ma 0.1 (tau 0.50605,
     Re 1600): before the vortex stretching has built up enstrophy, the
     kinetic energy decays at the laminar rate of the initial mode. The
     velocity field is an eigenfunction of the Laplacian with eigenvalue
     -3/L^2 (L = n / 2 pi), so dKE/dt = -2 nu Omega gives 6 nu / L^2.
 
-    The initial field carries no pressure correction, so acoustic waves
-    trade kinetic with compression energy at the rate the viscous decay
-    has (a fit of the whole kinetic energy over 100 steps gives 6 times the
-    laminar rate). Those waves are curl-free: the energy of the
-    divergence-free part of the flow is free of them and decays by
-    viscosity, at the laminar rate until stretching changes the enstrophy
-    at second order in t / t_c (t_c = L / U0 = 580 steps)."""
+    Two effects ride on it and are removed. (1) The populations start at
+    equilibrium with omega = 1.976, so for tens of steps the moments ring
+    with alternating sign (an initial layer): the fit starts at step 40.
+    (2) The initial field has no pressure correction; the pressure
+    imbalance, at wavevectors 2 and 2 sqrt 2 (in units of 1/L), radiates
+    sound that trades about 0.1% of the energy with the vortex at the
+    acoustic frequencies 2 c_s / L and 2 sqrt 2 c_s / L (c_s = sqrt(gamma
+    theta0)), as much as the viscous loss in 400 steps. So the energy of the
+    divergence-free part of the flow, sampled every 20 steps from 40 to 400,
+    is fitted with a - b t plus those two oscillations, and b / a is held
+    to 6 nu / L^2 and to the measured viscous dissipation 2 nu <Omega> / KE
+    (the enstrophy grows by 5% by step 400) within 3%."""
     n, tau, ma = 256, 0.50605, 0.1
     _, _, th = L.lattice()
     u0 = ma * np.sqrt(5.0 / 3.0 * th)
     F = wl.taylor_green(n, u0)
-    ctx = L.init([(n, n, n, tau)], *F.absolute(th), storage=storage)
-    ts, ke = [], []
-    for t in range(0, 101, 20):
-        if t:
-            ctx.step(20)
+    ctx = L.init([(n, n, n, tau)], *F.absolute(th), storage="f32")
+    ts, ke, om = [], [], []
+    done = 0
+    for t in range(40, 401, 20):
+        ctx.step(t - done)
+        done = t
         m = ctx.moments()
-        ke.append(solenoidal_kinetic_energy(m, n))
-        ts.append(t)
+        k, o = solenoidal_energy_enstrophy(m, n)
         del m
+        ts.append(t)
+        ke.append(k)
+        om.append(o)
+    assert ctx.status() == 0
     ctx.free()
-    ts, ke = np.array(ts, dtype=float), np.array(ke)
+    ts, ke, om = np.array(ts, dtype=float), np.array(ke), np.array(om)
     nu = th * (tau - 0.5)
-    rate = 6.0 * nu / (n / (2 * np.pi)) ** 2
-    fit = -np.polyfit(ts, np.log(ke), 1)[0]
-    say("C3 early decay %s: laminar 6 nu/L^2 = %.4e per step; divergence-free kinetic energy over 100 steps "
-        "decays at %.4e (ratio %.4f); KE_sol/KE_sol(0) = %s" % (storage, rate, fit, fit / rate,
-                                                                 ["%.6f" % v for v in ke / ke[0]]))
-    assert abs(fit / rate - 1) < 5e-2
+    Lc = n / (2 * np.pi)
+    rate = 6.0 * nu / Lc ** 2
+    cs = np.sqrt(an.GAMMA * th)
+    cols = [np.ones_like(ts), -ts]
+    for w in (2 * cs / Lc, 2 * np.sqrt(2) * cs / Lc):
+        cols += [np.cos(w * ts), np.sin(w * ts)]
+    A = np.column_stack(cols)
+    c, *_ = np.linalg.lstsq(A, ke, rcond=None)
+    fit = c[1] / c[0]
+    dissip = float(np.mean(2 * nu * om / ke))
+    say("C3 early decay f32: laminar 6 nu/L^2 = %.4e per step; divergence-free kinetic energy decays at %.4e "
+        "(ratio %.4f; against the measured 2 nu <Omega>/KE = %.4e: %.4f); fit rms %.1e of KE"
+        % (rate, fit, fit / rate, dissip, fit / dissip, np.sqrt(np.mean((ke - A @ c) ** 2)) / c[0]))
+    assert abs(fit / rate - 1) < 3e-2
+    assert abs(fit / dissip - 1) < 3e-2
 
 
 def _line_pressure(ctx, n, y0, z0, s=0):
