@@ -760,8 +760,17 @@ struct StepParams {
 };
 
 // Counter-based random bits for stochastic rounding: one hash per node and
-// step ("lowbias32", C. Wellons, hash-prospector), then Marsaglia's
-// xorshift32 (J. Stat. Softw. 8(14), 2003) for successive 32-bit words.
+// step ("lowbias32", C. Wellons, hash-prospector), then successive 32-bit
+// words by a Weyl sequence, word k = h + (k + 1) * 2^32/phi (mod 2^32; the
+// increment is the golden-ratio constant of multiplicative hashing, Knuth,
+// TAOCP vol. 3, 6.4). Each word is the uniform hash plus a constant, so
+// every rounding draws uniform bits; the words of one node and step are
+// shifts of each other, which leaves each rounding unbiased. One add per
+// word instead of xorshift's six shifts and xors: the 16-bit kernels with
+// stochastic rounding are partly arithmetic-bound, and more so at the
+// clock they settle to under sustained load.
+constexpr uint32_t WEYL_STEP = 0x9e3779b9u;
+
 __host__ __device__ inline uint32_t hash32(uint32_t x)
 {
     x ^= x >> 16;
@@ -772,13 +781,7 @@ __host__ __device__ inline uint32_t hash32(uint32_t x)
     return x;
 }
 
-__host__ __device__ inline uint32_t xorshift32(uint32_t& s)
-{
-    s ^= s << 13;
-    s ^= s >> 17;
-    s ^= s << 5;
-    return s;
-}
+__host__ __device__ constexpr uint32_t weyl_word(uint32_t h, uint32_t k) { return h + (k + 1u) * WEYL_STEP; }
 
 // FP32 x + d rounded stochastically: s = RN(x + d) with exact residual e
 // (Fast2Sum, |x| >= |d|), then RN(s + e + (r - 1/2) ulp(s)) rounds the exact

@@ -501,12 +501,12 @@ __device__ __forceinline__ void collide_encode(typename ST::R x[Q], typename ST:
         // random bits per (node of the context, step): the step is the
         // launch's own count plus, in graph replays, a device-held base
         const uint32_t step = p.step + (p.step_base ? *p.step_base : 0u);
-        rs = hash32(nid ^ hash32(step * 0x9e3779b9u + p.seed)) | 1u;
+        rs = hash32(nid ^ hash32(step * WEYL_STEP + p.seed));
     }
     static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         if constexpr (SR) {
-            if constexpr (q % 2 == 0) rw = xorshift32(rs);
+            if constexpr (q % 2 == 0) rw = weyl_word(rs, uint32_t(q / 2));
             const uint32_t rb = (q % 2 == 0) ? (rw & 0xffffu) : (rw >> 16);
             // 16-bit storage: populations in pairs sharing one random word
             // (measured 2-3% faster, except with the series equilibrium,
