@@ -56,6 +56,11 @@ def parse():
                          "under each DIR): per step-kernel instance, the median of each counter over its dispatches "
                          "and the figures derived from them")
     ap.add_argument("--kernel-filter", default="k_step", help="kernels summarized by --summarize-counters")
+    ap.add_argument("--hbm-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="only write the HBM-traffic summary under profiles/ from four rocprofv3 --pmc outputs")
+    ap.add_argument("--trace-summary", nargs=3, metavar=("TRACE_DIR", "BENCH_STDERR", "OUT_MD"),
+                    help="only write a kernel-trace summary from a rocprofv3 --kernel-trace output of the "
+                         "trace run (bench_log_cmd) and that run's stderr")
     return ap.parse_args()
 
 
@@ -175,6 +180,147 @@ def summarize_counters(dirs, kernel_filter):
                 out.append("| %s | %.4g |" % (name, v))
         out.append("")
     print("\n".join(out))
+
+
+# rocprofv3 recipes of the committed summaries (run from the repository root)
+HBM_RUN = "python3 bench.py --steps 3 --warmup 10 --no-cpu-baseline --no-batch --forms f16s+sr,f32,f16s"
+COPY_RUN = "python3 bench.py --copy-reference 4"
+TUNE_ROUNDS, TUNE_REPS = 3, 4  # the autotuner: 3 rounds, each configuration timed with 1 + 3 dispatches
+
+
+def _counter_rows(d):
+    import csv
+    rows = []
+    for path in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        with open(path) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _per_dispatch(rows, counter):
+    """{dispatch id: (kernel name, value)} for one counter, in dispatch order."""
+    out = {}
+    for r in rows:
+        if r["Counter_Name"] == counter:
+            out[int(r["Dispatch_Id"])] = (r["Kernel_Name"].split("(")[0].strip(), float(r["Counter_Value"]))
+    return dict(sorted(out.items()))
+
+
+def hbm_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, nvariants=6):
+    """HBM bytes per launch of every launch configuration of the step
+    kernels of HBM_RUN (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, each
+    in a run of its own), scaled by what the same counters read for the
+    runtime's copy of 4 GiB (COPY_RUN). The dispatches of each form come in
+    a fixed order: the warmup (10 steps), then the autotuner's rounds over
+    (variant, XCD remap) pairs, TUNE_REPS dispatches each; each
+    configuration keeps the median over its rounds. Writes COUNTERS (read
+    by the bench) and its markdown beside it."""
+    import statistics
+    gib4 = 4 << 30
+    cf = max(v for _, v in _per_dispatch(_counter_rows(copy_fetch_dir), "FETCH_SIZE").values())
+    cw = max(v for _, v in _per_dispatch(_counter_rows(copy_write_dir), "WRITE_SIZE").values())
+    scale_f, scale_w = gib4 / (cf * 1024), gib4 / (cw * 1024)
+    fetch = _per_dispatch(_counter_rows(fetch_dir), "FETCH_SIZE")
+    write = _per_dispatch(_counter_rows(write_dir), "WRITE_SIZE")
+    forms = HBM_RUN.split("--forms ")[1].split(",")
+    # the step dispatches of the run, form after form
+    seq_f = [(k, v) for k, v in fetch.values() if "k_step<" in k]
+    seq_w = [(k, v) for k, v in write.values() if "k_step<" in k]
+    per_form = 10 + TUNE_ROUNDS * nvariants * 2 * TUNE_REPS + 10 + 3
+    if len(seq_f) != per_form * len(forms) or len(seq_w) != len(seq_f):
+        raise SystemExit("expected %d step dispatches, found %d fetch / %d write"
+                         % (per_form * len(forms), len(seq_f), len(seq_w)))
+    n = 512 ** 3 * 2
+    out = {"source_sha256": kernel_source_hash(), "scale": {"fetch": scale_f, "write": scale_w},
+           "commands": ["rocprofv3 --pmc FETCH_SIZE -f csv -d %s -o f -- %s" % (fetch_dir, HBM_RUN),
+                        "rocprofv3 --pmc WRITE_SIZE -f csv -d %s -o w -- %s" % (write_dir, HBM_RUN),
+                        "rocprofv3 --pmc FETCH_SIZE -f csv -d %s -o cf -- %s" % (copy_fetch_dir, COPY_RUN),
+                        "rocprofv3 --pmc WRITE_SIZE -f csv -d %s -o cw -- %s" % (copy_write_dir, COPY_RUN)],
+           "forms": {}}
+    lines = []
+    for i, form in enumerate(forms):
+        base = i * per_form + 10
+        eb = 2 if form.startswith(("f16s", "bf16s")) else 4 if form.startswith("f32") else 8
+        algo = ALGO_VALUES_PER_NODE // 2 * eb * n
+        recs = {}
+        for v in range(nvariants):
+            for x in (0, 1):
+                idx = [base + rnd * nvariants * 2 * TUNE_REPS + (2 * v + x) * TUNE_REPS + k
+                       for rnd in range(TUNE_ROUNDS) for k in range(TUNE_REPS)]
+                names = {seq_f[j][0] for j in idx}
+                if len(names) != 1:
+                    raise SystemExit("dispatch order does not match the autotuner's for %s v%d r%d" % (form, v, x))
+                fb = statistics.median(seq_f[j][1] for j in idx) * 1024 * scale_f
+                wb = statistics.median(seq_w[j][1] for j in idx) * 1024 * scale_w
+                blk, hints = None, None
+                kname = names.pop()
+                recs[(v, x)] = (kname, fb, wb)
+        out["forms"][form] = {}
+        for (v, x), (kname, fb, wb) in recs.items():
+            targs = kname.split("<")[1].split(">")[0].split(",")
+            blk, hints = int(targs[2]), int(targs[3])
+            out["forms"][form]["%d,%d,%d" % (blk, hints, x)] = {"kernel": kname, "fetch_bytes": fb,
+                                                                "write_bytes": wb, "variant": v}
+            lines.append("| `%s` (XCD remap %s) | %s | %.2f | %.2f | %.2f | %.3f | %.3f |"
+                         % (kname, "on" if x else "off", form, fb / 1e9, wb / 1e9, algo / 1e9, fb / algo, wb / algo))
+    with open(COUNTERS, "w") as fh:
+        json.dump(out, fh, indent=1)
+    md = ["# HBM traffic of the fused step kernel, 512^3 acoustic pulse (rocprofv3 counters)", "",
+          "Commands (from the repository root on one MI355X; each counter in a run of its own):", ""]
+    md += ["    " + c for c in out["commands"]]
+    md += ["", "Summary written by `python3 bench.py --hbm-summary %s %s %s %s`." % (fetch_dir, write_dir,
+                                                                                   copy_fetch_dir, copy_write_dir),
+           "",
+           "Scale: the runtime's copy of 4 GiB reads FETCH_SIZE = %.0f KiB and WRITE_SIZE = %.0f KiB per dispatch, "
+           "so bytes = FETCH_SIZE KiB x 1024 x %.3f and WRITE_SIZE KiB x 1024 x %.3f." % (cf, cw, scale_f, scale_w),
+           "",
+           "Algorithmic bytes per launch: 41 loads + 41 stores per node, %d nodes. Every launch variant with the XCD "
+           "remap off and on (the autotuner's dispatches: %d rounds of %d, medians)." % (n, TUNE_ROUNDS, TUNE_REPS),
+           "",
+           "| kernel | form | fetched GB | written GB | algorithmic read = write GB | fetch / algorithmic | "
+           "write / algorithmic |", "|---|---|---|---|---|---|---|"] + lines
+    with open(COUNTERS.replace(".json", ".md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
+def trace_summary(trace_dir, bench_log, steps, out_md):
+    """Kernel-trace summary (rocprofv3 --kernel-trace CSV): per step-kernel
+    instance, dispatches, mean duration over all and over the last `steps`
+    (for the chosen configuration of a form: its timed steps); bench_log is
+    the same run's stderr (the bench's own HIP-event figures)."""
+    import csv
+    rows = []
+    for path in sorted(glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)):
+        with open(path) as fh:
+            rows += list(csv.DictReader(fh))
+    per = {}
+    for r in sorted(rows, key=lambda r: int(r["Start_Timestamp"])):
+        k = r["Kernel_Name"].split("(")[0].strip()
+        if "k_step" in k or "k_stream_free" in k:
+            per.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6)
+    with open(bench_log) as fh:
+        blog = [l.rstrip() for l in fh if l.startswith("#")]
+    md = ["# Step kernels on the 512^3 acoustic pulse: rocprofv3 kernel trace", "",
+          "Command (from the repository root on one MI355X):", "",
+          "    rocprofv3 --kernel-trace --stats -f csv -d %s -o kt -- %s" % (trace_dir, bench_log_cmd(steps)), "",
+          "Summary written by `python3 bench.py --trace-summary %s <stderr of that run> %d %s`." % (
+              trace_dir, steps, out_md), "",
+          "bench.py's own HIP-event timing in the same run:", ""] + ["    " + l for l in blog] + [
+          "", "| kernel | dispatches | mean ms (all) | mean ms (last %d) |" % steps, "|---|---|---|---|"]
+    for k, d in sorted(per.items(), key=lambda kv: -len(kv[1])):
+        last = d[-steps:]
+        md.append("| `%s` | %d | %.3f | %.3f |" % (k, len(d), sum(d) / len(d), sum(last) / len(last)))
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
+TRACE_FORMS = "f16s+sr,f32,f16s,bf16s+sr,f16s+sr+e1,f16s+sr+elbm"
+
+
+def bench_log_cmd(steps):
+    return "python3 bench.py --no-cpu-baseline --steps %d --forms %s" % (steps, TRACE_FORMS)
 
 
 def parse_form(form):
@@ -369,6 +515,12 @@ def main():
     args = parse()
     if args.summarize_counters:
         summarize_counters(args.summarize_counters, args.kernel_filter)
+        return
+    if args.hbm_summary:
+        hbm_summary(*args.hbm_summary)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary[0], args.trace_summary[1], args.steps, args.trace_summary[2])
         return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
