@@ -206,7 +206,7 @@ def _per_dispatch(rows, counter):
     return dict(sorted(out.items()))
 
 
-def hbm_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, nvariants=6):
+def hbm_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     """HBM bytes per launch of every launch configuration of the step
     kernels of HBM_RUN (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, each
     in a run of its own), scaled by what the same counters read for the
@@ -215,7 +215,11 @@ def hbm_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, nvariants=
     (variant, XCD remap) pairs, TUNE_REPS dispatches each; each
     configuration keeps the median over its rounds. Writes COUNTERS (read
     by the bench) and its markdown beside it."""
+    import re
     import statistics
+    from paper_1909_08406_amd import lbm
+    nvariants = lbm.num_variants()
+    step_kernel = re.compile(r"lbm::k_step(_lds)?<")
     gib4 = 4 << 30
     cf = max(v for _, v in _per_dispatch(_counter_rows(copy_fetch_dir), "FETCH_SIZE").values())
     cw = max(v for _, v in _per_dispatch(_counter_rows(copy_write_dir), "WRITE_SIZE").values())
@@ -224,8 +228,8 @@ def hbm_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, nvariants=
     write = _per_dispatch(_counter_rows(write_dir), "WRITE_SIZE")
     forms = HBM_RUN.split("--forms ")[1].split(",")
     # the step dispatches of the run, form after form
-    seq_f = [(k, v) for k, v in fetch.values() if "k_step<" in k]
-    seq_w = [(k, v) for k, v in write.values() if "k_step<" in k]
+    seq_f = [(k, v) for k, v in fetch.values() if step_kernel.search(k)]
+    seq_w = [(k, v) for k, v in write.values() if step_kernel.search(k)]
     per_form = 10 + TUNE_ROUNDS * nvariants * 2 * TUNE_REPS + 10 + 3
     if len(seq_f) != per_form * len(forms) or len(seq_w) != len(seq_f):
         raise SystemExit("expected %d step dispatches, found %d fetch / %d write"

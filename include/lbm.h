@@ -339,8 +339,11 @@ typedef struct {
 /* Number of step-kernel variants. No device needed. */
 int lbm_num_variants(void);
 
-/* Block size and hint flags (1: non-temporal loads, 2: non-temporal stores)
- * of a variant. No device needed. Errors: LBM_E_ARG. */
+/* Block size and hint flags of a variant: 1 non-temporal loads, 2
+ * non-temporal stores, 4 source rows staged in LDS (16-bit storage, per-box
+ * launches of boxes whose nx is a multiple of the block size; elsewhere the
+ * variant runs the plain kernel of its block size). No device needed.
+ * Errors: LBM_E_ARG. */
 int lbm_variant_desc(int32_t variant, int32_t *block_threads, uint32_t *flags);
 
 /* Select / read the launch configuration of a context. */

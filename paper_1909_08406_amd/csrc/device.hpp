@@ -139,6 +139,25 @@ __device__ inline uint32_t pull_src(const Nbr& nb)
     }
 }
 
+// pull_src split into the part that does not depend on x (sublattice, y
+// and z moves; the same for every node of an x-row) and the move along x:
+// the node at x pulls population q from x + pull_dx<q>(s) (periodic) of the
+// row at offset pull_row<q>.
+template <int q>
+__device__ inline uint32_t pull_row(const Nbr& nb)
+{
+    constexpr HalfVel v = VEL[q];
+    if constexpr (v.shell == 5) return nb.sh + nb.zh[v.z > 0 ? 0 : 1] + nb.yh[v.y > 0 ? 0 : 1];
+    else return nb.so + nb.zo[2 - v.z / 2] + nb.yo[2 - v.y / 2];
+}
+template <int q>
+__device__ inline int pull_dx(uint32_t s)
+{
+    constexpr HalfVel v = VEL[q];
+    if constexpr (v.shell == 5) return v.x > 0 ? (s ? 0 : -1) : (s ? 1 : 0);
+    else return -(v.x / 2);
+}
+
 // ---------------------------------------------------------------------------
 // Arithmetic helpers per compute type.
 // ---------------------------------------------------------------------------

@@ -692,6 +692,89 @@ __global__ __launch_bounds__(BLK) void k_step(const typename ST::T* __restrict__
     step_node<ST, NEWTON, FL, SR, MODEL>(reinterpret_cast<const char*>(fin), reinterpret_cast<char*>(fout), p, n);
 }
 
+// LDS-staged step, 16-bit storage, for tiles of BLK nodes that lie within
+// one x-row (BLK divides nx). Every node of such a tile pulls population q
+// from the same source row (same sublattice, y and z moves), shifted along
+// x by pull_dx<q> in [-2, 2]. The block first copies, for each q, that
+// row's segment [x0 - 2, x0 + BLK + 2) (periodic in x) into LDS with
+// aligned 32-bit loads: one load instruction covers the tile's span for two
+// populations, and the first 2Q threads fetch one halo word each. All loads
+// are issued before the first LDS write, so they are in flight together.
+// Each node then reads its 41 values from LDS, and reads them again for the
+// relaxation rather than keeping them in registers. The per-node arithmetic
+// and the stores are step_node's.
+template <class ST, int NEWTON, int BLK, int FL, bool SR, int MODEL = MODEL_E2>
+__global__ __launch_bounds__(BLK) void k_step_lds(const typename ST::T* __restrict__ fin,
+                                                  typename ST::T* __restrict__ fout, StepParams p)
+{
+    using R = typename ST::R;
+    using T = typename ST::T;
+    static_assert(sizeof(T) == 2 && (MODEL & MODEL_WALLS) == 0, "LDS staging: 16-bit storage, periodic boxes");
+    static_assert(2 * Q <= BLK, "one halo word per thread");
+    constexpr int BODY = BLK / 2;  // 32-bit words of the tile's own span of a row
+    constexpr int SEG = BODY + 2;  // and one word (two elements) of halo on either side
+    constexpr int NP = (Q + 1) / 2;  // passes of two populations
+    __shared__ uint32_t stage[Q * SEG];
+    const uint32_t blk = p.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t n0 = blk * BLK;
+    const Coord c0 = decode(n0, p.g);  // the tile's row; c0.x is a multiple of BLK
+    Nbr nb;
+    make_nbr(p.g, c0, nb, uint32_t(sizeof(T)));
+    const char* src = reinterpret_cast<const char*>(fin);
+    const uint64_t qbytes = uint64_t(p.g.qs) * sizeof(T);
+    const uint32_t t = threadIdx.x;
+    // byte offsets within a row: the body from x0, the halo words at x0 - 2 and x0 + BLK
+    const uint32_t xb = c0.x * 2u;
+    const uint32_t xlo = (c0.x == 0 ? p.g.nx - 2u : c0.x - 2u) * 2u;
+    const uint32_t xhi = (c0.x + BLK == p.g.nx ? 0u : c0.x + BLK) * 2u;
+    const uint32_t odd = t / BODY, w = t - odd * BODY;  // population of the pair, word of the body
+    // bodies: pass j copies populations 2j (threads below BODY) and 2j + 1
+    // (the last pass, with Q odd, copies population Q - 1 twice)
+    uint32_t body[NP];
+    static_for<NP>([&](auto jc) {
+        constexpr int qa = 2 * decltype(jc)::value, qb = qa + 1 < Q ? qa + 1 : qa;
+        const uint32_t q = odd ? uint32_t(qb) : uint32_t(qa);
+        const uint32_t row = odd ? pull_row<qb>(nb) : pull_row<qa>(nb);
+        body[decltype(jc)::value] = *reinterpret_cast<const uint32_t*>(src + q * qbytes + uint64_t(row + xb + 4 * w));
+    });
+    // halos: thread t < 2Q fetches the left (t even) or right word of population t / 2
+    const uint32_t hq = t >> 1, right = t & 1u;
+    uint32_t halo = 0;
+    if (t < 2u * Q) {
+        uint32_t row = pull_row<0>(nb);
+        static_for<Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if constexpr (q > 0) row = hq == uint32_t(q) ? pull_row<q>(nb) : row;
+        });
+        halo = *reinterpret_cast<const uint32_t*>(src + hq * qbytes + uint64_t(row + (right ? xhi : xlo)));
+    }
+    static_for<NP>([&](auto jc) {
+        constexpr int qa = 2 * decltype(jc)::value, qb = qa + 1 < Q ? qa + 1 : qa;
+        stage[(odd ? qb : qa) * SEG + 1 + w] = body[decltype(jc)::value];
+    });
+    if (t < 2u * Q) stage[hq * SEG + (right ? SEG - 1 : 0)] = halo;
+    __syncthreads();
+    const uint16_t* st16 = reinterpret_cast<const uint16_t*>(stage);
+    // element of population q for this node: segment index t + 2 + dx
+    auto lds_val = [&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const int dx = c0.s ? pull_dx<q>(1u) : pull_dx<q>(0u);
+        return ST::decode(__builtin_bit_cast(T, st16[q * 2 * SEG + int(t) + 2 + dx]));
+    };
+    R x[Q];
+    T out[Q];
+    static_for<Q>([&](auto qc) { x[decltype(qc)::value] = lds_val(qc); });
+    flag_saturated<ST, SR>(x, p);
+    const uint32_t n = n0 + t;
+    collide_encode<ST, NEWTON, SR, MODEL>(x, out, p, p.node0 + n, lds_val);
+    char* dst = reinterpret_cast<char*>(fout);
+    const uint32_t nbytes = n * uint32_t(sizeof(T));
+    static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        st_hint(reinterpret_cast<T*>(dst + q * qbytes + uint64_t(nbytes)), out[q], FL & FL_NT_STORE);
+    });
+}
+
 // Collisionless streaming (free flight): every population moves along its
 // link unchanged, the update of Sec. II without the collision term. The
 // same pull addressing, loads and stores as k_step (T: the stored type), a

@@ -1041,6 +1041,7 @@ int lbm_stream_free(lbm_ctx* ctx, int32_t n)
             case 3: by_type(integral_constant<int, 128>{}, integral_constant<int, 0>{}); break;
             case 4: by_type(integral_constant<int, 256>{}, integral_constant<int, FL_NT_STORE>{}); break;
             case 5: by_type(integral_constant<int, 1024>{}, integral_constant<int, 0>{}); break;
+            case 6: by_type(integral_constant<int, 256>{}, integral_constant<int, 0>{}); break;  // plain pulls
             default: rc = LBM_E_ARG; break;
         }
         if (rc) return rc;

@@ -22,6 +22,10 @@ constexpr int blk_index(int blk) { return blk == 128 ? 0 : blk == 256 ? 1 : blk 
 // Cache-policy hints of a variant.
 constexpr int FL_NT_LOAD = 1;   // non-temporal loads (streamed once)
 constexpr int FL_NT_STORE = 2;  // non-temporal stores
+// Stage each tile's source rows in LDS (k_step_lds): 16-bit storage, per-box
+// launches of boxes whose x-rows hold whole tiles; elsewhere the variant
+// runs the plain kernel of its block size.
+constexpr int FL_LDS = 4;
 
 // Step-kernel launch variants: block size and cache-policy hints. Every
 // variant computes the same per-node arithmetic.
@@ -30,7 +34,7 @@ struct VariantDesc {
     int fl;
 };
 constexpr VariantDesc VARIANTS[] = {
-    {256, 0}, {256, FL_NT_LOAD | FL_NT_STORE}, {512, 0}, {128, 0}, {256, FL_NT_STORE}, {1024, 0},
+    {256, 0}, {256, FL_NT_LOAD | FL_NT_STORE}, {512, 0}, {128, 0}, {256, FL_NT_STORE}, {1024, 0}, {256, FL_LDS},
 };
 constexpr int NVARIANTS = int(sizeof(VARIANTS) / sizeof(VARIANTS[0]));
 

@@ -21,6 +21,7 @@ inline int step_with_variant(int v, F&& f)
         case 3: f(integral_constant<int, 128>{}, integral_constant<int, 0>{}); break;
         case 4: f(integral_constant<int, 256>{}, integral_constant<int, FL_NT_STORE>{}); break;
         case 5: f(integral_constant<int, 1024>{}, integral_constant<int, 0>{}); break;
+        case 6: f(integral_constant<int, 256>{}, integral_constant<int, FL_LDS>{}); break;
         default: return -1;
     }
     return 0;
@@ -51,9 +52,10 @@ int enqueue_step_impl(const StepLaunch& L)
             constexpr int MODEL = decltype(model)::value;
             constexpr int BLK = decltype(blk)::value;
             constexpr int FL = decltype(fl)::value;
+            constexpr int FLP = FL & ~FL_LDS;  // the plain kernel's hints
             if (L.schedule == 1) {
                 const int i = blk_index(BLK);
-                hipLaunchKernelGGL((k_step_batch<ST, NEWTON, BLK, FL, SR, MODEL>), dim3(uint32_t(L.ntiles[i])),
+                hipLaunchKernelGGL((k_step_batch<ST, NEWTON, BLK, FLP, SR, MODEL>), dim3(uint32_t(L.ntiles[i])),
                                    dim3(BLK), 0, L.stream, in, out, L.table, L.tiles[i], L.xcd_remap, L.step,
                                    L.step_base);
             } else {
@@ -62,8 +64,16 @@ int enqueue_step_impl(const StepLaunch& L)
                     p.step = L.step;
                     p.step_base = L.step_base;
                     p.xcd_remap = L.xcd_remap;
-                    hipLaunchKernelGGL((k_step<ST, NEWTON, BLK, FL, SR, MODEL>),
-                                       dim3(uint32_t((L.nodes[b] + BLK - 1) / BLK)), dim3(BLK), 0, L.stream,
+                    const dim3 grid(uint32_t((L.nodes[b] + BLK - 1) / BLK));
+                    if constexpr ((FL & FL_LDS) != 0 && sizeof(T) == 2 && (MODEL & MODEL_WALLS) == 0) {
+                        // whole tiles per x-row (the grid then has no ragged tile)
+                        if (p.g.nx % BLK == 0) {
+                            hipLaunchKernelGGL((k_step_lds<ST, NEWTON, BLK, FL, SR, MODEL>), grid, dim3(BLK), 0,
+                                               L.stream, in + L.offset[b], out + L.offset[b], p);
+                            continue;
+                        }
+                    }
+                    hipLaunchKernelGGL((k_step<ST, NEWTON, BLK, FLP, SR, MODEL>), grid, dim3(BLK), 0, L.stream,
                                        in + L.offset[b], out + L.offset[b], p);
                 }
             }

@@ -72,6 +72,34 @@ def test_batched_schedule_identical_to_per_box(L, storage, sr):
         assert np.array_equal(got, ref), (v, x)
 
 
+@pytest.mark.parametrize("storage,sr", [("f16s", False), ("f16s", True), ("bf16s", False), ("bf16s", True)])
+def test_lds_staged_variant_identical_to_plain(L, storage, sr):
+    """The LDS-staged variant (its tiles' source rows copied into LDS first)
+    steps boxes whose x extent is a multiple of its 256-node tile, including
+    rows that wrap in y and z (ny, nz of 1 and 2) and a box whose single row
+    is one tile; a box with nx = 96 takes the plain kernel. Every box ends bit
+    for bit where the plain per-node pulls take it, with and without the XCD
+    remap. (Launch variants apply to the energy-conserving model; the other
+    models run the default launch.)"""
+    boxes = [(256, 3, 2, 0.6), (512, 2, 1, 0.53), (256, 1, 1, 0.9), (96, 4, 2, 0.7)]
+    lds = [v for v in range(L.num_variants()) if L.variant_desc(v)[1] & 4]
+    assert lds, "no LDS-staged variant"
+    _, _, th = L.lattice()
+    fields = [wl.random_state(b[0], b[1], b[2], seed=90 + i, amp_u=0.03, amp_rho=1e-3, amp_theta=1e-3)
+              for i, b in enumerate(boxes)]
+    cat = wl.concat(fields)
+    out = []
+    for variant, remap in [(0, 1)] + [(v, x) for v in lds for x in (0, 1)]:
+        ctx = L.init(boxes, cat[0], cat[1], cat[2], cat[3], cat[4] * th, storage=storage, stochastic=sr)
+        ctx.set_tuning(schedule="per_box", variant=variant, xcd_remap=remap)
+        ctx.step(9)
+        out.append(ctx.get_populations())
+        assert ctx.status() == 0
+        ctx.free()
+    for o in out[1:]:
+        assert np.array_equal(o, out[0])
+
+
 @pytest.mark.parametrize("storage,sr", [("f64", False), ("f32", True), ("f16s", True), ("bf16s", False)])
 @pytest.mark.parametrize("schedule", ["batched", "per_box"])
 def test_graph_replays_identical_to_eager(L, storage, sr, schedule):
