@@ -35,7 +35,7 @@ def parse():
                     help="untimed steps before tuning and timing: long enough (about 4 s of the FP16 step) for "
                          "the clock to settle under sustained load")
     ap.add_argument("--n", type=int, default=512, help="cells per edge of the periodic box")
-    ap.add_argument("--forms", default="f16s+sr,f32,f16s,f32+sr,f32s,bf16s+sr,f16s+sr+e1,f32+e1,f16s+sr+elbm,f32+elbm",
+    ap.add_argument("--forms", default="f16s+sr,f32,f16s,f32+sr,f32s,bf16s+sr,f16s+sr+e1,f32+e1,f16s+sr+elbm,f32+elbm,f64",
                     help="storage forms ('+sr': stochastic rounding, '+e1': series equilibrium E1 instead of "
                          "the entropic E2, '+elbm': entropic path length, '+walls': kinetic walls normal to y); "
                          "the first is the headline")
