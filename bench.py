@@ -298,11 +298,13 @@ def trace_summary(trace_dir, bench_log, steps, out_md):
     for path in sorted(glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)):
         with open(path) as fh:
             rows += list(csv.DictReader(fh))
-    per = {}
+    per, res = {}, {}
     for r in sorted(rows, key=lambda r: int(r["Start_Timestamp"])):
         k = r["Kernel_Name"].split("(")[0].strip()
         if "k_step" in k or "k_stream_free" in k:
             per.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6)
+            res[k] = tuple(r.get(c, "") for c in ("VGPR_Count", "SGPR_Count", "LDS_Block_Size", "Scratch_Size",
+                                                  "Workgroup_Size_X"))
     with open(bench_log) as fh:
         blog = [l.rstrip() for l in fh if l.startswith("#")]
     md = ["# Step kernels on the 512^3 acoustic pulse: rocprofv3 kernel trace", "",
@@ -311,10 +313,15 @@ def trace_summary(trace_dir, bench_log, steps, out_md):
           "Summary written by `python3 bench.py --trace-summary %s <stderr of that run> %d %s`." % (
               trace_dir, steps, out_md), "",
           "bench.py's own HIP-event timing in the same run:", ""] + ["    " + l for l in blog] + [
-          "", "| kernel | dispatches | mean ms (all) | mean ms (last %d) |" % steps, "|---|---|---|---|"]
+          "", "The last columns are the trace's own fields per dispatch (`VGPR_Count` and `SGPR_Count` in the "
+          "profiler's allocation units, not registers; LDS bytes per block, scratch bytes per lane, threads per "
+          "block). The compiler's register counts are in `profiles/k_step_resources.md`.", "",
+          "| kernel | dispatches | mean ms (all) | mean ms (last %d) | VGPR_Count | SGPR_Count | LDS | scratch | "
+          "block |" % steps, "|---|---|---|---|---|---|---|---|---|"]
     for k, d in sorted(per.items(), key=lambda kv: -len(kv[1])):
         last = d[-steps:]
-        md.append("| `%s` | %d | %.3f | %.3f |" % (k, len(d), sum(d) / len(d), sum(last) / len(last)))
+        md.append("| `%s` | %d | %.3f | %.3f | %s |" % (k, len(d), sum(d) / len(d), sum(last) / len(last),
+                                                       " | ".join(res[k])))
     with open(out_md, "w") as fh:
         fh.write("\n".join(md) + "\n")
     print("\n".join(md))
