@@ -452,19 +452,20 @@ public:
         FILE* f = std::fopen(path, "a+");
         if (!f) return LBM_E_ARG;
         std::rewind(f);
-        char key[4096];
+        // one entry per line: key and four integers; other lines are skipped
+        char line[8192], key[4096], extra[2];
         lbm_tuning t;
-        for (;;) {
-            const int n = std::fscanf(f, "%4095s %d %d %d %d", key, &t.variant, &t.xcd_remap, &t.schedule,
-                                      &t.graph_steps);
-            if (n == EOF) break;
-            if (n != 5) {
-                int c;
+        while (std::fgets(line, sizeof line, f)) {
+            if (!std::strchr(line, '\n') && !std::feof(f)) {
+                int c;  // over-long line: drop its remainder
                 while ((c = std::fgetc(f)) != EOF && c != '\n') {
                 }
                 continue;
             }
-            if (tuning_valid(t)) map_[key] = t;
+            if (std::sscanf(line, "%4095s %d %d %d %d %1s", key, &t.variant, &t.xcd_remap, &t.schedule,
+                            &t.graph_steps, extra) == 5 &&
+                tuning_valid(t))
+                map_[key] = t;
         }
         std::fclose(f);
         file_ = path;

@@ -1,3 +1,4 @@
+#define _POSIX_C_SOURCE 200809L /* mkstemp, fdopen */
 /* Host-only exercise of the C-ABI (test helper): every entry point that
  * needs no device, with valid and invalid arguments, for a build of the
  * library whose host code carries AddressSanitizer. Prints "ok" and exits 0
@@ -113,6 +114,34 @@ int main(void)
     EXPECT(lbm_status(NULL) == LBM_E_ARG);
     EXPECT(lbm_stream(NULL) == NULL);
     lbm_free(NULL);
+
+    /* the tuning cache file: valid entries, a one-token line, extra tokens,
+       out-of-range values and an over-long line */
+    {
+        char path[] = "/tmp/lbm_tune_asan_XXXXXX";
+        int fd = mkstemp(path);
+        EXPECT(fd >= 0);
+        FILE *f = fdopen(fd, "w");
+        fprintf(f, "keyA 0 1 0 0\nlonely\nkeyB 1 0 1 16\nkeyC 1 0 1 16 extra\nkeyD 99 0 0 0\nkeyE 0 1 0 3\n");
+        for (int i = 0; i < 20000; ++i) fputc('x', f);
+        fprintf(f, " 0 1 0 0\nkeyF 2 1 1 64\n");
+        fclose(f);
+        EXPECT(lbm_tune_cache_clear() == LBM_OK);
+        EXPECT(lbm_tune_cache_file(path) == LBM_OK);
+        EXPECT(lbm_tune_cache_count() == 3); /* keyA, keyB, keyF */
+        EXPECT(lbm_tune_cache_file(NULL) == LBM_OK);
+        EXPECT(lbm_tune_cache_clear() == LBM_OK && lbm_tune_cache_count() == 0);
+        remove(path);
+    }
+    /* the allocation-free totals reject bad arguments before any device call */
+    {
+        double dev_out[5];
+        lbm_box big = {65536, 65536, 2, 0, 0.6};
+        EXPECT(lbm_totals_noalloc(NULL, LBM_F32, &box, 60, 1.0, 0, NULL, dev_out) == LBM_E_ARG);
+        EXPECT(lbm_totals_noalloc(dev_out, 9, &box, 60, 1.0, 0, NULL, dev_out) == LBM_E_ARG);
+        EXPECT(lbm_totals_noalloc(dev_out, LBM_F32, &box, 59, 1.0, 0, NULL, dev_out) == LBM_E_ARG);
+        EXPECT(lbm_totals_noalloc(dev_out, LBM_F16_SHIFT, &big, (1ull << 33), 1.0, 0, NULL, dev_out) == LBM_E_ARG);
+    }
 
     if (fails) return 1;
     printf("ok\n");

@@ -92,3 +92,24 @@ def test_init_rejects_unrealisable_fields_before_device_work(L):
 def test_strerror_covers_codes(L):
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.lib().lbm_strerror(code).decode() != "unknown error"
+
+
+def test_tune_cache_file_parsing(L, tmp_path):
+    """The tuning cache file (host code, no device): one entry per line of a
+    key and four integers. Lines with one token, extra tokens, values out of
+    range (variant, odd graph length) or beyond the line buffer are skipped
+    without disturbing the lines around them."""
+    path = tmp_path / "tune.txt"
+    nv = L.num_variants()
+    lines = ["keyA 0 1 0 0", "lonely", "keyB 1 0 1 16", "keyC 1 0 1 16 extra", "keyD %d 0 0 0" % nv,
+             "keyE 0 1 0 3", "x" * 20000 + " 0 1 0 0", "keyF %d 1 1 64" % (nv - 1)]
+    path.write_text("\n".join(lines) + "\n")
+    L.tune_cache_file(None)
+    L.tune_cache_clear()
+    try:
+        L.tune_cache_file(path)
+        assert L.tune_cache_count() == 3  # keyA, keyB, keyF
+    finally:
+        L.tune_cache_file(None)
+        L.tune_cache_clear()
+    assert L.tune_cache_count() == 0
