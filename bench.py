@@ -64,11 +64,18 @@ def parse():
     return ap.parse_args()
 
 
+# What the step kernels' HBM traffic depends on: their sources, their launch
+# code and the buffer layout (not the rest of the host code).
+STEP_SOURCES = ("device.hpp", "kernels.hpp", "lattice.hpp", "layout.hpp", "step_launch.hpp", "step_tu.hpp",
+                "step_*.hip")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1909_08406_amd", "csrc", "*"))):
+    csrc = os.path.join(ROOT, "paper_1909_08406_amd", "csrc")
+    for p in sorted({f for pat in STEP_SOURCES for f in glob.glob(os.path.join(csrc, pat))}):
         with open(p, "rb") as fh:
-            h.update(fh.read())
+            h.update(os.path.basename(p).encode() + b"\0" + fh.read())
     return h.hexdigest()
 
 

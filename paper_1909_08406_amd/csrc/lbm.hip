@@ -21,6 +21,7 @@
 
 #include "../../include/lbm.h"
 #include "kernels_io.hpp"
+#include "layout.hpp"
 #include "step_launch.hpp"
 
 using namespace lbm;
@@ -28,9 +29,6 @@ using namespace lbm;
 namespace {
 
 constexpr uint64_t STAGING_MAX = 256ull << 20;  // bytes of the host<->device staging area
-constexpr uint64_t ALIGN = 256;
-
-uint64_t align_up(uint64_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 int elem_bytes(int storage)
 {
@@ -75,21 +73,6 @@ uint32_t model_of(uint32_t flags)
                           : (flags & LBM_FLAG_SERIES_EQUILIBRIUM) ? uint32_t(MODEL_SERIES) : uint32_t(MODEL_E2);
     return base | ((flags & LBM_FLAG_ENTROPIC) ? uint32_t(MODEL_ENTROPIC) : 0u) |
            ((flags & LBM_FLAG_WALLS) ? uint32_t(MODEL_WALLS) : 0u);
-}
-
-// Elements from one q-block of a box to the next: the block rounded up to
-// 256 bytes, plus 1 MiB + 256 bytes for 16-bit storage when the block is a
-// multiple of 1 MiB. Without it the 41 streams of a step sit at the same
-// address modulo a large power of two (a 512^3 FP16 q-block is 2^29 bytes);
-// measured on MI355X at 512^3: FP16-shifted+SR 9.25 -> 8.69 ms per step,
-// BF16-shifted+SR 9.65 -> 9.09 ms, while FP32 and FP64 gained nothing (FP64
-// lost 2%), so they keep the plain stride.
-constexpr uint64_t QPAD_16 = (1u << 20) + 256;
-uint32_t qstride(uint64_t nodes, int eb)
-{
-    const uint64_t bytes = align_up(nodes * uint64_t(eb));
-    const uint64_t pad = (eb == 2 && bytes % (1u << 20) == 0) ? QPAD_16 : 0;
-    return uint32_t((bytes + pad) / uint64_t(eb));
 }
 
 int check_boxes(const lbm_box* boxes, int32_t nboxes, const lbm_opts* opts)
