@@ -177,6 +177,13 @@ def summarize_counters(dirs, kernel_filter):
                     derived.append(("%s / SQ_WAVE_CYCLES" % c, med[c] / med["SQ_WAVE_CYCLES"]))
             if "TA_TA_BUSY_sum" in med:
                 derived.append(("TA busy share (TA_TA_BUSY_sum per TA-cycle)", med["TA_TA_BUSY_sum"] / (CUS * cyc)))
+        if gui and "TCC_BUSY_sum" in med:
+            derived.append(("L2 channel busy share (TCC_BUSY_sum per channel-cycle, 16 channels per XCD)",
+                            med["TCC_BUSY_sum"] / (16 * XCDS * gui / XCDS)))
+        if w:
+            for c in ("TCP_TCC_READ_REQ_sum", "TCP_TCC_WRITE_REQ_sum", "TCC_REQ_sum"):
+                if c in med:
+                    derived.append(("%s per wavefront" % c, med[c] / w))
         if "TCC_HIT_sum" in med and "TCC_MISS_sum" in med:
             derived.append(("L2 hit rate", med["TCC_HIT_sum"] / max(1.0, med["TCC_HIT_sum"] + med["TCC_MISS_sum"])))
         if derived:
