@@ -19,6 +19,9 @@ holds pre-collision ones (collide then push); their conserved moments are
 equal, and the oracle's collide_field() of its state gives the GPU's
 populations, which are compared element by element.
 """
+import os
+import time
+
 import numpy as np
 import pytest
 
@@ -645,6 +648,38 @@ def test_taylor_green_64_vs_oracle(L, orc, ma, tau, steps, storage, tol):
         % (ma, storage, steps, err, ["%.2e" % e for e in pe]))
     assert err <= tol
     assert max(pe) <= TGV_PERT_BAR[storage], pe
+
+
+@pytest.mark.skipif(os.environ.get("LBM_FULL_ORACLE") != "1",
+                    reason="about 10 minutes of host time (the oracle at 256^3); run with LBM_FULL_ORACLE=1")
+def test_taylor_green_256_100_steps_vs_oracle(L, orc):
+    """The 256^3 Taylor-Green problem itself (Ma 0.1, tau 0.50605, Re 1600),
+    FP32 storage and arithmetic, against a full FP64 oracle run of all
+    33,554,432 nodes over 100 steps: normwise moment error (1e-5) and per
+    field against its own perturbation (1e-3, the 64^3 runs' bar). Skipped
+    in the default run for its host time."""
+    n, tau, steps, chunk = 256, 0.50605, 100, 10
+    _, _, th = L.lattice()
+    F = wl.taylor_green(n, 0.1 * np.sqrt(5.0 / 3.0 * th))
+    ctx = gpu_run(L, (n, n, n), tau, F, steps, "f32")
+    m_gpu = ctx.moments()
+    assert ctx.status() == 0
+    ctx.free()
+    _, _, th_o = orc.lattice()
+    f = orc.init(n, n, n, *F.absolute(th_o))
+    m_init = orc.moment_fields(f)
+    t0 = time.time()
+    for done in range(0, steps, chunk):
+        f = orc.run(n, n, n, 1.0 / tau, f, chunk)
+        say("C3 256^3 oracle: %d of %d steps, %.0f s" % (done + chunk, steps, time.time() - t0))
+    m_ref = orc.moment_fields(f)
+    del f
+    err = moment_error(m_gpu, m_ref)
+    pe = perturbation_errors(m_gpu, m_ref, m_init)
+    say("C3 256^3 f32, %d steps: normwise moment error %.2e, per field / perturbation %s"
+        % (steps, err, ["%.2e" % e for e in pe]))
+    assert err <= 1e-5
+    assert max(pe) <= TGV_PERT_BAR["f32"], pe
 
 
 @pytest.mark.parametrize("storage,sr,tol", [("f64", False, 1e-12), ("f32", False, 1e-5), ("f16s", True, 1e-5)])
