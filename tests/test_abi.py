@@ -54,6 +54,7 @@ def test_argument_validation(L):
     assert L.workspace_size(ok, "f32") > 0
     bad = [
         ([(8, 8, 8, 0.5)], {}),                 # tau_lb must exceed 1/2
+        ([], {}),                               # no boxes
         ([(0, 8, 8, 0.6)], {}),                 # empty box
         ([(8, -1, 8, 0.6)], {}),
         ([(8, 8, 8, float("nan"))], {}),

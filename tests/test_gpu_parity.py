@@ -304,6 +304,33 @@ def test_uniform_equilibrium_fixed_point(L):
         assert np.max(np.abs(f1 - f0)) <= tol * np.max(f0), storage
 
 
+def test_zero_and_negative_step_counts(L):
+    """Zero steps (eager or with graph replays set up) leave the held state
+    and the step count as they are; a negative count is rejected before any
+    launch, and the state is again unchanged."""
+    boxes = [(5, 3, 2, 0.6), (1, 1, 1, 0.7)]
+    F = [wl.random_state(*b[:3], seed=3 + i) for i, b in enumerate(boxes)]
+    _, _, th = L.lattice()
+    cat = wl.concat(F)
+    ctx = L.init(boxes, cat[0], cat[1], cat[2], cat[3], cat[4] * th, storage="f16s", stochastic=True)
+    done = 0
+    for g, n in ((0, 3), (4, 5)):  # 5 steps with graphs of 4: one replay, one eager step
+        ctx.set_tuning(graph_steps=g)
+        ctx.step(n)
+        done += n
+        f0 = ctx.get_populations()
+        ctx.step(0)
+        ctx.stream_free(0)
+        for call in (ctx.step, ctx.stream_free):
+            with pytest.raises(L.LbmError) as e:
+                call(-1)
+            assert e.value.code == L.E_ARG
+        assert ctx.info()["steps_done"] == done
+        assert np.array_equal(ctx.get_populations(), f0), g
+    assert ctx.status() == 0
+    ctx.free()
+
+
 def test_nonfinite_state_is_flagged(L):
     """Unrealisable populations set from the host make the step flag the
     node; the kernel itself completes normally."""
