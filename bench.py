@@ -98,22 +98,36 @@ def measured_traffic(form, block, hints, xcd_remap):
             "scale": d.get("scale"), "source": os.path.relpath(COUNTERS, ROOT)}
 
 
-def copy_reference(torch, gib, reps=5):
-    """A plain copy kernel of known size: bytes read = bytes written = GIB GiB."""
+def time_copy(torch, gib, reps=5, lbm=None):
+    """A plain device-to-device copy of known size: bytes read = bytes
+    written = GIB GiB. The runtime's copy, or with `lbm` the library's own
+    copy kernel (16-byte words)."""
     n = int(gib * (1 << 30))
     a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
     b = torch.empty_like(a)
-    b.copy_(a)
+    if lbm is None:
+        copy = lambda: b.copy_(a)  # noqa: E731
+    else:
+        stream = torch.cuda.current_stream()
+        copy = lambda: lbm.device_copy(a.data_ptr(), b.data_ptr(), n, stream)  # noqa: E731
+    copy()
     torch.cuda.synchronize()
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s.record()
     for _ in range(reps):
-        b.copy_(a)
+        copy()
     e.record()
     e.synchronize()
     ms = s.elapsed_time(e) / reps
-    print(json.dumps({"copy_reference_bytes_read": n, "copy_reference_bytes_written": n, "ms": ms,
-                      "gbs_read_plus_write": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_read": n, "bytes_written": n, "ms": ms, "gbs_read_plus_write": 2 * n / (ms * 1e-3) / 1e9}
+
+
+def copy_reference(torch, gib, reps=5):
+    r = time_copy(torch, gib, reps)
+    print(json.dumps({"copy_reference_bytes_read": r["bytes_read"], "copy_reference_bytes_written": r["bytes_written"],
+                      "ms": r["ms"], "gbs_read_plus_write": r["gbs_read_plus_write"]}), flush=True)
 
 
 # MI355X: 256 CUs of 4 SIMDs in 8 XCDs (GRBM_GUI_ACTIVE is summed over the XCDs)
@@ -580,6 +594,15 @@ def main():
                                                       pc["step_over_pattern"]), file=sys.stderr, flush=True)
         runs.append(r)
     del F
+    # what a plain copy reaches on this device: the achievable HBM rate
+    # beside the published peak
+    cp = time_copy(torch, 4, reps=20, lbm=lbm)
+    copy_ceiling = {"kernel": "lbm::k_copy16, plain copy of 4 GiB (lbm_device_copy)", "ms": cp["ms"],
+                    "achieved": cp["gbs_read_plus_write"], "frac": cp["gbs_read_plus_write"] / HBM_PEAK_GBS,
+                    "step_over_copy": runs[0]["gbs"] / cp["gbs_read_plus_write"]}
+    print("# plain copy of 4 GiB: %.0f GB/s read + write (%.3f of 8 TB/s); %s step at %.3f of it"
+          % (cp["gbs_read_plus_write"], copy_ceiling["frac"], runs[0]["form"], copy_ceiling["step_over_copy"]),
+          file=sys.stderr, flush=True)
     batch = None
     if not args.no_batch:
         batch = {"workload": "256 periodic standing-wave boxes, edges from {16,24,32,48,64,96}, k 1..4, "
@@ -627,7 +650,8 @@ def main():
                      "traffic_bytes_per_launch": traffic,
                      "kernel": "lbm::k_step (%s)" % head["form"],
                      "algorithmic_bytes_per_launch": head["bytes_per_launch"],
-                     "pattern_ceiling": pattern_ceiling(head)},
+                     "pattern_ceiling": pattern_ceiling(head),
+                     "copy_ceiling": copy_ceiling},
         "cpu_baseline": cpu,
         "batch": batch,
     }

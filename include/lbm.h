@@ -226,6 +226,21 @@ int lbm_step(lbm_ctx *ctx, int32_t n);
  */
 int lbm_stream_free(lbm_ctx *ctx, int32_t n);
 
+/*
+ * Measurement helper, outside the method: copies `bytes` bytes from the
+ * device pointer src to the device pointer dst with the library's plain
+ * copy kernel (16-byte words, fully coalesced, no arithmetic). Its rate,
+ * bytes read plus bytes written over the kernel's time, is what a
+ * streaming kernel reaches on the device; the step's rate is reported
+ * beside it and beside the published HBM peak. bytes: a multiple of 16
+ * (0 does nothing); src and dst 16-byte aligned, not overlapping, both
+ * owned by the caller. Queued on `stream` (a hipStream_t, NULL for the
+ * null stream) without synchronising.
+ * Errors: LBM_E_ARG (null or misaligned pointers, a size not a multiple of
+ * 16 or above (2^31 - 1) x 4096, overlapping ranges), LBM_E_HIP.
+ */
+int lbm_device_copy(const void *src, void *dst, uint64_t bytes, void *stream);
+
 /* Wait for all work queued on the context stream. */
 int lbm_synchronize(lbm_ctx *ctx);
 

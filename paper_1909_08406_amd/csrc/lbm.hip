@@ -1036,6 +1036,20 @@ int lbm_stream_free(lbm_ctx* ctx, int32_t n)
 #endif
 }
 
+int lbm_device_copy(const void* src, void* dst, uint64_t bytes, void* stream)
+{
+    const uintptr_t s = reinterpret_cast<uintptr_t>(src), d = reinterpret_cast<uintptr_t>(dst);
+    if (!src || !dst || bytes % 16 != 0 || (s | d) % 16 != 0) return LBM_E_ARG;
+    if (bytes == 0) return LBM_OK;
+    if (s < d + bytes && d < s + bytes) return LBM_E_ARG;  // overlapping ranges
+    const uint64_t n = bytes / 16;
+    const uint64_t blocks = (n + BLOCK - 1) / BLOCK;
+    if (blocks > 0x7fffffffull) return LBM_E_ARG;
+    hipLaunchKernelGGL(k_copy16, dim3(uint32_t(blocks)), dim3(BLOCK), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n);
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+}
+
 int lbm_synchronize(lbm_ctx* ctx)
 {
     if (!ctx) return LBM_E_ARG;

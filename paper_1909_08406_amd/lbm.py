@@ -104,6 +104,7 @@ SIGNATURES = {
     "lbm_autotune_ex": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_float),
                                        ctypes.POINTER(TuneResult)]),
     "lbm_stream_free": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "lbm_device_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_uint64, _vp]),
     "lbm_totals_noalloc": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(Box), ctypes.c_uint64, ctypes.c_double,
                                           ctypes.c_int32, _vp, _vp]),
     "lbm_tune_cache_file": (ctypes.c_int, [ctypes.c_char_p]),
@@ -431,6 +432,15 @@ def totals_noalloc(f_ptr, storage, dims, qstride, rho0=1.0, shift_exp=0, stream=
                                     else int(storage), ctypes.byref(box), int(qstride), float(rho0), int(shift_exp),
                                     ctypes.c_void_p(h) if h else None, ctypes.c_void_p(int(out_ptr))),
            "lbm_totals_noalloc")
+
+
+def device_copy(src_ptr, dst_ptr, nbytes, stream=None):
+    """lbm_device_copy: the library's plain copy of nbytes bytes between
+    device pointers (a measurement helper), queued on `stream` (a
+    torch.cuda.Stream, a raw handle or None)."""
+    h = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    _check(lib().lbm_device_copy(ctypes.c_void_p(int(src_ptr)), ctypes.c_void_p(int(dst_ptr)), int(nbytes),
+                                 ctypes.c_void_p(h) if h else None), "lbm_device_copy")
 
 
 def tune_cache_file(path):

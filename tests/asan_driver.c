@@ -142,6 +142,16 @@ int main(void)
         EXPECT(lbm_totals_noalloc(dev_out, LBM_F32, &box, 59, 1.0, 0, NULL, dev_out) == LBM_E_ARG);
         EXPECT(lbm_totals_noalloc(dev_out, LBM_F16_SHIFT, &big, (1ull << 33), 1.0, 0, NULL, dev_out) == LBM_E_ARG);
     }
+    /* the plain copy rejects bad arguments before any launch; 0 bytes is a no-op */
+    {
+        _Alignas(16) unsigned char a[64], b[64];
+        EXPECT(lbm_device_copy(NULL, b, 16, NULL) == LBM_E_ARG);
+        EXPECT(lbm_device_copy(a, NULL, 16, NULL) == LBM_E_ARG);
+        EXPECT(lbm_device_copy(a, b, 24, NULL) == LBM_E_ARG);       /* not a multiple of 16 */
+        EXPECT(lbm_device_copy(a + 8, b, 16, NULL) == LBM_E_ARG);   /* misaligned */
+        EXPECT(lbm_device_copy(a, a + 16, 32, NULL) == LBM_E_ARG);  /* overlapping */
+        EXPECT(lbm_device_copy(a, b, 0, NULL) == LBM_OK);
+    }
 
     if (fails) return 1;
     printf("ok\n");

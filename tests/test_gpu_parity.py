@@ -140,6 +140,26 @@ def test_free_streaming_is_the_oracle_permutation(L, orc, storage, sr):
             off += N
 
 
+def test_device_copy(L):
+    """lbm_device_copy (the measurement copy kernel) copies exactly the
+    requested bytes, ragged tails included, and nothing beyond them; bad
+    arguments are rejected before any launch."""
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(5)
+    for nbytes in (16, 16 * 1023, 16 * (4 * 256 * 3 + 5)):
+        a = torch.randint(0, 256, (nbytes + 256,), dtype=torch.uint8, device="cuda", generator=g)
+        b = torch.zeros_like(a)
+        L.device_copy(a.data_ptr(), b.data_ptr(), nbytes)
+        torch.cuda.synchronize()
+        assert torch.equal(b[:nbytes], a[:nbytes]), nbytes
+        assert not bool(b[nbytes:].any()), nbytes
+    for src, dst, n in ((a.data_ptr() + 8, b.data_ptr(), 16), (a.data_ptr(), b.data_ptr(), 24),
+                        (a.data_ptr(), a.data_ptr() + 16, 32)):
+        with pytest.raises(L.LbmError) as e:
+            L.device_copy(src, dst, n)
+        assert e.value.code == L.E_ARG
+
+
 def test_init_equilibrium_matches_oracle(L, orc):
     """The closed-form partition-function Newton (GPU) and the generic 5x5
     Newton (oracle) give the same entropic equilibrium, up to Ma ~ 0.4."""
