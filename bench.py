@@ -329,17 +329,17 @@ def trace_summary(trace_dir, bench_log, steps, out_md):
     per, res = {}, {}
     for r in sorted(rows, key=lambda r: int(r["Start_Timestamp"])):
         k = r["Kernel_Name"].split("(")[0].strip()
-        if "k_step" in k or "k_stream_free" in k:
+        if "k_step" in k or "k_stream_free" in k or "k_copy16" in k:
             per.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6)
             res[k] = tuple(r.get(c, "") for c in ("VGPR_Count", "SGPR_Count", "LDS_Block_Size", "Scratch_Size",
                                                   "Workgroup_Size_X"))
     with open(bench_log) as fh:
         blog = [l.rstrip() for l in fh if l.startswith("#")]
-    md = ["# Step kernels on the 512^3 acoustic pulse: rocprofv3 kernel trace", "",
+    md = ["# Step kernels on the 512^3 acoustic pulse: rocprofv3 kernel trace of the default bench run", "",
           "Command (from the repository root on one MI355X):", "",
           "    rocprofv3 --kernel-trace --stats -f csv -d %s -o kt -- %s" % (trace_dir, bench_log_cmd(steps)), "",
-          "Summary written by `python3 bench.py --trace-summary %s <stderr of that run> %d %s`." % (
-              trace_dir, steps, out_md), "",
+          "Summary written by `python3 bench.py --steps %d --trace-summary %s <stderr of that run> %s`." % (
+              steps, trace_dir, out_md), "",
           "bench.py's own HIP-event timing in the same run:", ""] + ["    " + l for l in blog] + [
           "", "The last columns are the trace's own fields per dispatch (`VGPR_Count` and `SGPR_Count` in the "
           "profiler's allocation units, not registers; LDS bytes per block, scratch bytes per lane, threads per "
@@ -355,11 +355,9 @@ def trace_summary(trace_dir, bench_log, steps, out_md):
     print("\n".join(md))
 
 
-TRACE_FORMS = "f16s+sr,f32,f16s,bf16s+sr,f16s+sr+e1,f16s+sr+elbm"
-
-
 def bench_log_cmd(steps):
-    return "python3 bench.py --no-cpu-baseline --steps %d --forms %s" % (steps, TRACE_FORMS)
+    """The traced command: the default bench run, with its step count."""
+    return "python3 bench.py --steps %d" % steps
 
 
 def parse_form(form):
