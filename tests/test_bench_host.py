@@ -129,3 +129,32 @@ def test_source_hash_follows_the_step_kernels_only(tmp_path, monkeypatch):
         h1 = bench.kernel_source_hash()
         assert h1 != h0, f
         h0 = h1
+
+
+def test_trace_summary_means_over_the_last_steps(tmp_path):
+    """Per kernel instance: all dispatches and the last `steps` of them
+    (the timed steps), the bench's own lines carried over; other kernels
+    are left out."""
+    rows = []
+    t = 0
+    for k, durs in (("void lbm::k_step<A>(x)", [2.0] * 5 + [1.0] * 3), ("void lbm::k_copy16(x)", [0.5, 0.5]),
+                    ("void lbm::k_init<A>(x)", [9.0])):
+        for d in durs:
+            rows.append({"Kernel_Name": k, "Start_Timestamp": t, "End_Timestamp": t + int(d * 1e6),
+                         "VGPR_Count": 8, "SGPR_Count": 16, "LDS_Block_Size": 0, "Scratch_Size": 0,
+                         "Workgroup_Size_X": 256})
+            t += int(d * 1e6) + 1000
+    os.makedirs(tmp_path / "kt")
+    with open(tmp_path / "kt" / "kt_kernel_trace.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+    log = tmp_path / "bench.err"
+    log.write_text("# f16s+sr: 1.000 ms/step\nnoise\n")
+    out = tmp_path / "kt.md"
+    bench.trace_summary(str(tmp_path / "kt"), str(log), 3, str(out))
+    md = out.read_text()
+    assert "    # f16s+sr: 1.000 ms/step" in md and "noise" not in md
+    assert "| `void lbm::k_step<A>` | 8 | 1.625 | 1.000 | 8 | 16 | 0 | 0 | 256 |" in md
+    assert "| `void lbm::k_copy16` | 2 | 0.500 | 0.500 |" in md
+    assert "k_init" not in md
